@@ -1,0 +1,125 @@
+"""Pins of the oracle's C0IP matrix (not GPU).
+
+* exact SymPy 1D factors + the paper's Kronecker representation
+  (Sec. 4, eqs. ``c0iptensorvp``, ``c0iptensorvp3D``, ``localsolverbila``)
+  against the oracle's 2D/3D explicit quadrature;
+* consistency: a smooth polynomial in H^2_0 that lies in V_l solves the
+  discrete problem exactly (the method is consistent, Sec. 2);
+* symmetry and positive definiteness (Proposition, eq. ``hnorm``);
+* the energy-error rate h^(k-1) (eq. ``energyerror``) for the clamped
+  solution prod sin^2(pi x_i).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import sympy as S
+
+import oracle as O
+from tests import sym1d
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 2), (2, 2, 4), (2, 3, 4), (2, 4, 2), (3, 2, 2), (3, 3, 2)])
+def test_kronecker_representation(dim, k, N):
+    A = O.assemble(dim, k, N).toarray()
+    K = sym1d.kron_sum(dim, k, N)
+    assert np.abs(A - K).max() <= 1e-12 * np.abs(K).max()
+    At = O.assemble(dim, k, N, bulk="diag").toarray()
+    Kt = sym1d.kron_sum(dim, k, N, separable=True)
+    assert np.abs(At - Kt).max() <= 1e-12 * np.abs(Kt).max()
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 8), (2, 3, 4), (2, 5, 4), (2, 7, 2), (3, 2, 4), (3, 3, 2)])
+def test_symmetric_positive_definite(dim, k, N):
+    A = O.assemble(dim, k, N)
+    assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+    free = ~O.boundary_mask(dim, k, N)
+    Af = A[free][:, free].toarray()
+    np.linalg.cholesky(Af)  # raises if not SPD
+    At = O.assemble(dim, k, N, bulk="diag")[free][:, free].toarray()
+    np.linalg.cholesky(At)
+
+
+def _poly_solution(dim):
+    xs = S.symbols("x0:%d" % dim)
+    u = S.Integer(1)
+    for x in xs:
+        u = u * (x * (1 - x)) ** 2
+    lap = lambda w: sum(S.diff(w, x, 2) for x in xs)  # noqa: E731
+    f = S.expand(lap(lap(u)))
+    return xs, u, f
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 4, 2), (2, 4, 4), (2, 5, 2), (3, 4, 2)])
+def test_consistency_polynomial_in_space(dim, k, N):
+    """u = prod (x_i (1-x_i))^2 is in H^2_0 and, for k >= 4, in V_l; C0IP
+    is consistent, so its nodal interpolant solves A U = F exactly."""
+    xs, u, f = _poly_solution(dim)
+    fu = S.lambdify(xs, u, "numpy")
+    ff = S.lambdify(xs, f, "numpy")
+    A = O.assemble(dim, k, N)
+    F = O.load_vector(dim, k, N, lambda X: ff(*[X[..., m] for m in range(dim)]) + 0 * X[..., 0], q=k + 3)
+    n1 = k * N + 1
+    z = O.gll_nodes(k)
+    x1 = np.concatenate([c / N + z[:-1] / N for c in range(N)] + [[1.0]])
+    mi = O.node_multi_index(dim, n1)
+    U = fu(*[x1[mi[:, m]] for m in range(dim)])
+    res = A @ U - F
+    assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(F)
+
+
+def test_consistency_is_sensitive_to_face_term_signs():
+    """A(gamma) = C + gamma P.  For the smooth u: P U = 0 (no jumps) and the
+    face part of C is far from zero, so a flipped sign of the consistency
+    terms of eq. ``bfc0ip`` would break A U = F."""
+    dim, k, N = 2, 4, 2
+    xs, u, f = _poly_solution(dim)
+    fu = S.lambdify(xs, u, "numpy")
+    ff = S.lambdify(xs, f, "numpy")
+    n1 = k * N + 1
+    z = O.gll_nodes(k)
+    x1 = np.concatenate([c / N + z[:-1] / N for c in range(N)] + [[1.0]])
+    mi = O.node_multi_index(dim, n1)
+    U = fu(*[x1[mi[:, m]] for m in range(dim)])
+    F = O.load_vector(dim, k, N, lambda X: ff(X[..., 0], X[..., 1]), q=k + 3)
+    C = O.assemble(dim, k, N, gamma=0.0)
+    P = O.assemble(dim, k, N, gamma=1.0) - C
+    Kb = O.assemble(dim, k, N, faces=False)
+    assert np.linalg.norm(C @ U - F) < 1e-10 * np.linalg.norm(F)
+    assert np.linalg.norm(P @ U) < 1e-10 * np.linalg.norm(F)
+    face = (C - Kb) @ U
+    assert np.linalg.norm(face) > 0.1 * np.linalg.norm(F)
+    assert np.linalg.norm((Kb - (C - Kb)) @ U - F) > 0.1 * np.linalg.norm(F)
+
+
+@pytest.mark.parametrize("dim,k,Ns,tol", [(2, 2, (4, 8, 16), 0.15), (2, 3, (4, 8, 16), 0.15),
+                                         (2, 4, (4, 8, 16), 0.2), (3, 2, (2, 4, 8), 0.25)])
+def test_energy_error_rate(dim, k, Ns, tol):
+    errs = []
+    for N in Ns:
+        A = O.assemble(dim, k, N)
+        F = O.manufactured_rhs(dim, k, N)
+        free = ~O.boundary_mask(dim, k, N)
+        u = np.zeros(A.shape[0])
+        u[free] = spla.spsolve(A[free][:, free].tocsc(), F[free])
+        errs.append(O.energy_error(dim, k, N, u))
+    rate = math.log2(errs[-2] / errs[-1])
+    assert rate >= (k - 1) - tol, (errs, rate)
+    assert rate <= (k - 1) + 0.5, (errs, rate)
+
+
+def test_windowed_rows_equal_global_rows():
+    dim, k, N = 2, 3, 8
+    A = O.assemble(dim, k, N).tocsr()
+    win = O.Window(dim, k, N, lo=[2, 0], hi=[7, 4])
+    Aw = O.assemble(dim, k, N, window=win).tocsr()
+    rows = np.where(win.exact_rows())[0]
+    assert rows.size > 10
+    x = np.random.default_rng(3).uniform(-1, 1, A.shape[0])
+    yg = A @ x
+    yw = Aw @ x[win.gidx]
+    assert np.allclose(yw[rows], yg[win.gidx[rows]], rtol=1e-13, atol=1e-12 * np.abs(yg).max())
+    # and a row just outside the exact set differs (the window really is cut)
+    bad = np.where(~win.exact_rows() & win.free)[0]
+    assert np.abs(yw[bad] - yg[win.gidx[bad]]).max() > 1e-6 * np.abs(yg).max()
