@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the C0IP biharmonic hot path on one MI355X.
+
+Workload: 2D unit square, 512 x 512 cells, Q3 (2,362,369 DoFs incl.
+boundary), clamped, gamma = k(k+1), seeded uniform[-1,1] right-hand side.
+A step is one flexible-GMRES(50) solve to relative residual 1e-8,
+preconditioned by a float32 V-cycle (additive vertex-patch smoother, 1 pre-
+and 1 post-step, omega = 1/4; float64 coarse solve): it exercises every row
+of the hot path (operator, residual, patch gather, fast-diagonalisation
+solve, scatter, transfers, coarse solve, V-cycle, Arnoldi).  The value is
+DoFs solved per second.  Alongside: float64 operator and smoother apply
+rates (cold HBM: rotating buffer sets bigger than the 256 MB last-level
+cache), the all-float64 solve, the roofline entry for the dominant kernel
+(timed with events on the library's stream) and the CPU oracle baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--k", type=int, default=3)
+    ap.add_argument("--N", type=int, default=512)
+    ap.add_argument("--omega", type=float, default=0.25)
+    ap.add_argument("--reps", type=int, default=30, help="kernel timing repetitions")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-N", type=int, default=64, help="cells per direction of the oracle sample")
+    return ap.parse_args()
+
+
+def time_kernel(fn, sets, reps, torch):
+    """Average ms per launch of fn(set) over reps launches, rotating buffer
+    sets; events on the current stream (the library's stream)."""
+    for i in range(3):
+        fn(sets[i % len(sets)])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        fn(sets[i % len(sets)])
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(k, N, omega):
+    """The oracle (plain NumPy/SciPy, float64, dense LU patch solves) solving
+    the same problem class at a smaller size: DoFs solved per second."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2412_05082_amd.inputs import seeded_vector
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    dim = 2
+    b = seeded_vector(dim, k, N, 0)
+    A = O.assemble(dim, k, N)
+    H = O.Hierarchy(dim, k, N, omega=omega)
+    t0 = time.perf_counter()
+    x, info = O.fgmres(A, b, H.vcycle, rtol=1e-8, restart=50)
+    dt = time.perf_counter() - t0
+    n = b.size
+    return {"value": n / dt, "unit": "DoFs/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle FGMRES(50)+float64 V-cycle solve to 1e-8, 2D Q{k} {N}x{N} cells ({n} DoFs), "
+                      f"{info['iterations']} its, {dt:.2f} s, setup excluded"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2412_05082_amd as P
+    from paper_2412_05082_amd.inputs import seeded_vector
+
+    dim, k, N = 2, args.k, args.N
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    b_np = seeded_vector(dim, k, N, 0)
+    x_np = seeded_vector(dim, k, N, 1)
+    n = b_np.size
+    b = torch.from_numpy(b_np).to(dev)
+    pmix = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F32)
+    p64 = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F64)
+
+    # --- per-kernel rates, cold HBM (rotating sets > 1 GB in total)
+    nsets = max(4, int(1.2e9 // (3 * 8 * n)) + 1)
+    sets64 = [(torch.from_numpy(x_np).to(dev), torch.empty(n, dtype=torch.float64, device=dev), b)
+              for _ in range(nsets)]
+    ms_mv = time_kernel(lambda s: pmix.apply_A(s[0], s[1]), sets64, args.reps, torch)
+    sm_sets = [(s[2], s[1]) for s in sets64]
+    ms_sm0 = time_kernel(lambda s: pmix.apply_smoother(s[0], s[1], x_is_zero=True), sm_sets, args.reps, torch)
+    ms_smx = time_kernel(lambda s: pmix.apply_smoother(s[0], s[1]), sm_sets, args.reps, torch)
+    del sets64, sm_sets
+    b32 = b.float()
+    sets32 = [(torch.from_numpy(x_np).float().to(dev), torch.zeros(n, dtype=torch.float32, device=dev), b32)
+              for _ in range(nsets)]
+    ms_mv32 = time_kernel(lambda s: pmix.apply_A(s[0], s[1]), sets32, args.reps, torch)
+    ms_smx32 = time_kernel(lambda s: pmix.apply_smoother(s[2], s[1]), sets32, args.reps, torch)
+    del sets32
+    torch.cuda.empty_cache()
+
+    # --- solves: all-float64 V-cycle vs float32 V-cycle (timed steps use the latter)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    info64 = None
+    for _ in range(max(1, args.warmup)):
+        info64 = p64.solve(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info64 = p64.solve(b, x)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+
+    for _ in range(args.warmup):
+        pmix.solve(b, x)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(pmix.solve(b, x))
+    torch.cuda.synchronize()
+    tsteps = time.perf_counter() - t0
+    ms_step = 1e3 * tsteps / args.steps
+    value = n * args.steps / tsteps
+
+    # dominant kernel of the float32 V-cycle: the smoother with residual
+    bytes_sm32 = 12.0 * n  # read x, read b, write x (float32)
+    achieved = bytes_sm32 / (ms_smx32 * 1e-3) / 1e9
+    out = {
+        "metric": "DoFs/s of C0IP mat-vec and patch smoother; FP32-vs-FP64 MG-GMRES solve time",
+        "value": value,
+        "unit": "DoFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded uniform[-1,1] right-hand side)",
+        "config": {"workload": f"2D Q{k} C0IP biharmonic, {N}x{N} cells, {n} DoFs; FGMRES(50) to 1e-8 "
+                               f"with a float32 V-cycle (AVS 1+1, omega {args.omega})",
+                   "dim": dim, "degree": k, "cells": N, "dofs": n},
+        "solve": {
+            "mixed": {"seconds": tsteps / args.steps, "iterations": infos[-1]["iterations"],
+                      "rel_res_true": infos[-1]["rel_res_true"], "seconds_vcycle": infos[-1]["seconds_vcycle"]},
+            "fp64": {"seconds": t64, "iterations": info64["iterations"], "rel_res_true": info64["rel_res_true"],
+                     "seconds_vcycle": info64["seconds_vcycle"]},
+            "speedup_mixed_vs_fp64": t64 / (tsteps / args.steps),
+        },
+        "kernels": {
+            "matvec_f64": {"ms": ms_mv, "dofs_per_s": n / (ms_mv * 1e-3),
+                           "alg_GBs": 16.0 * n / (ms_mv * 1e-3) / 1e9},
+            "smoother_x0_f64": {"ms": ms_sm0, "dofs_per_s": n / (ms_sm0 * 1e-3),
+                                "alg_GBs": 16.0 * n / (ms_sm0 * 1e-3) / 1e9},
+            "smoother_f64": {"ms": ms_smx, "dofs_per_s": n / (ms_smx * 1e-3),
+                             "alg_GBs": 24.0 * n / (ms_smx * 1e-3) / 1e9},
+            "matvec_f32": {"ms": ms_mv32, "dofs_per_s": n / (ms_mv32 * 1e-3),
+                           "alg_GBs": 8.0 * n / (ms_mv32 * 1e-3) / 1e9},
+            "smoother_f32": {"ms": ms_smx32, "dofs_per_s": n / (ms_smx32 * 1e-3),
+                             "alg_GBs": 12.0 * n / (ms_smx32 * 1e-3) / 1e9},
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "float32 smoother step S(x,b) (residual + patch solve), 12 B/DoF"},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(k, args.cpu_N, args.omega)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

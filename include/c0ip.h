@@ -1,0 +1,162 @@
+/*
+ * c0ip.h - C ABI of libc0ip: the C0 interior-penalty (C0IP) biharmonic
+ * operator, the additive vertex-patch Schwarz smoother with fast-
+ * diagonalisation local solvers, the geometric multigrid V-cycle and the
+ * multigrid-preconditioned flexible GMRES solve, on one MI355X (gfx950).
+ *
+ * Problem (Sec. 2): Delta^2 u = f on [0,1]^d (d = 2, 3), clamped boundary
+ * (u = d_n u = 0), continuous Q_k Lagrange elements (Gauss-Lobatto nodes)
+ * on the uniform Cartesian mesh of N^d cells, discretised by the C0IP form
+ * of eq. bfc0ip with penalty gamma / h on every face.
+ *
+ * Vectors.  Every vector argument is a caller-owned, contiguous DEVICE
+ * buffer of num_dofs(level) = (k N_l + 1)^d entries in lexicographic node
+ * order (x fastest), boundary nodes included.  Boundary entries of inputs
+ * are ignored (treated as 0); boundary entries of outputs are written as 0.
+ * Element type is given by the c0ip_dtype argument (double or float).
+ *
+ * Levels.  Level l = 0..L has N_l = 2^(l+1) cells per direction (level 0:
+ * 2^d cells, one vertex patch); level L (= -1 in arguments) is the finest.
+ *
+ * Streams.  All device work of a handle is enqueued on the HIP stream given
+ * at creation (NULL = the default stream).  c0ip_apply_A,
+ * c0ip_apply_smoother and c0ip_vcycle are asynchronous; c0ip_solve
+ * synchronises the stream.  A handle must not be used from two host
+ * threads at once; calls on one handle are ordered by its stream.
+ *
+ * Errors.  Every call returns a c0ip_status; nothing aborts or throws
+ * across the ABI.  c0ip_last_error() describes the last failure of the
+ * calling thread.
+ */
+#ifndef C0IP_H
+#define C0IP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  C0IP_OK = 0,
+  C0IP_EINVAL = -1,          /* invalid argument (dimension, degree, size, pointer, level, option) */
+  C0IP_ENOMEM = -2,          /* device or host allocation failed */
+  C0IP_EHIP = -3,            /* a HIP runtime call or kernel launch failed (message in last_error) */
+  C0IP_NOT_CONVERGED = -4,   /* solve stopped at max_iters; x holds the last iterate, info is filled */
+  C0IP_ENAN = -5,            /* a non-finite value appeared in the Krylov iteration */
+  C0IP_EUNSUPPORTED = -6     /* valid request this build does not provide */
+} c0ip_status;
+
+typedef enum { C0IP_F64 = 0, C0IP_F32 = 1 } c0ip_dtype;
+
+typedef struct c0ip_problem c0ip_problem; /* opaque; owned by the library */
+
+/* Mesh and discretisation (Sec. 2): dim in {2,3}; n_cells = N, a power of
+ * two >= 2; degree = k in [2,7]; gamma = penalty constant (<= 0 selects
+ * k(k+1)), applied as gamma / h on interior and boundary faces. */
+typedef struct {
+  int dim;
+  int n_cells;
+  int degree;
+  double gamma;
+} c0ip_mesh_desc;
+
+/* Multigrid options (Sec. 3, Algorithm 1).
+ * omega: damping of the additive smoother (> 0; the paper uses 1/4 in 2D
+ *   and 0.1 in 3D; the overlap bounds it by 2^-d).
+ * pre_steps, post_steps: smoothing steps per level (>= 0).
+ * vcycle_dtype: precision of the V-cycle inside c0ip_solve (the coarse
+ *   solve is always float64).
+ * coarse_mode: 0 = exact level-0 solve (float64 dense inverse from a
+ *   Cholesky factorisation); 1 = one smoothing step with omega = 1.
+ * scatter_mode: 0 = owner-computes tiles (deterministic, no atomics); other
+ *   values are rejected with C0IP_EUNSUPPORTED. */
+typedef struct {
+  double omega;
+  int pre_steps, post_steps;
+  c0ip_dtype vcycle_dtype;
+  int coarse_mode;
+  int scatter_mode;
+} c0ip_mg_opts;
+
+/* Flexible GMRES options (Sec. 5.1: relative residual reduction 1e-8).
+ * rtol: stop when the Arnoldi residual estimate <= rtol * ||b||_2.
+ * max_iters: total iteration cap (>= 1).  restart: Krylov dimension m in
+ * [1, 64].  x0_is_zero: 1 = start from 0 (x is output only), 0 = start
+ * from the x passed in. */
+typedef struct {
+  double rtol;
+  int max_iters;
+  int restart;
+  int x0_is_zero;
+} c0ip_krylov_opts;
+
+typedef struct {
+  int iterations;      /* Arnoldi steps taken */
+  int converged;       /* 1 if the estimate met rtol */
+  double rel_res_est;  /* final Arnoldi estimate / ||b|| */
+  double rel_res_true; /* ||b - A x|| / ||b|| recomputed in float64 */
+  double frac_iters;   /* 8 n / (-log10(rel_res_est)) (Sec. 5.1) */
+  double seconds_total, seconds_vcycle, seconds_arnoldi;
+} c0ip_solve_info;
+
+/* Create a problem: level hierarchy, 1D matrices, patch eigenbases, coarse
+ * inverse, device tables and work space (Sec. 3-4).  opts may be NULL
+ * (omega 1/4 in 2D and 0.1 in 3D, 1 pre- and 1 post-step, float32
+ * V-cycle, exact coarse solve).  hip_stream is a hipStream_t or NULL.
+ * On success *out owns all device memory it allocated. */
+c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, void* hip_stream,
+                        c0ip_problem** out);
+/* Free the problem and every device allocation it owns (NULL is a no-op). */
+c0ip_status c0ip_destroy(c0ip_problem* p);
+
+/* Number of levels L+1, and DoFs of a level (level -1 = finest). */
+c0ip_status c0ip_num_levels(const c0ip_problem* p, int* n_levels);
+c0ip_status c0ip_num_dofs(const c0ip_problem* p, int level, int64_t* n_total);
+
+/* y = A_l x: the C0IP matrix of eq. bfc0ip on level l, applied matrix-free
+ * through its Kronecker form (Sec. 4, eqs. c0iptensorvp / c0iptensorvp3D).
+ * x and y must not overlap. */
+c0ip_status c0ip_apply_A(c0ip_problem* p, int level, c0ip_dtype dtype, const void* x, void* y);
+
+/* One step of the additive vertex-patch smoother (Sec. 3):
+ *   x <- x + omega * sum_v R_v^T A~_v^{-1} R_v (b - A_l x),
+ * with A~_v the separable local matrix of eq. localsolverbila inverted by
+ * fast diagonalisation (eq. inverse).  x_is_zero = 1 treats x as 0 on
+ * input (no residual is formed; x is output only).  b and x must not
+ * overlap. */
+c0ip_status c0ip_apply_smoother(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b, void* x,
+                                int x_is_zero);
+
+/* x = MG_L(0, b): one V-cycle of Algorithm 1 on the finest level in the
+ * given precision (coarse solve in float64), with the options' pre/post
+ * steps and damping. */
+c0ip_status c0ip_vcycle(c0ip_problem* p, c0ip_dtype dtype, const void* b, void* x);
+
+/* Solve A_L x = b by flexible GMRES in float64 right-preconditioned by one
+ * V-cycle (precision opts.vcycle_dtype) per iteration (Sec. 5.1, 5.2).
+ * b, x: float64 device vectors of the finest level.  info may be NULL.
+ * Returns C0IP_NOT_CONVERGED (x = last iterate) if max_iters is reached. */
+c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const double* b, double* x,
+                       c0ip_solve_info* info);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* c0ip_last_error(void);
+
+/* ---- host-only set-up inspection (no device needed) ----
+ * The library's 1D factors of the level with n_cells = N (Sec. 4, eqs.
+ * matrix1d, bulk1-bulk3, ev): dense (kN+1)^2 row-major host arrays M, L,
+ * B, boundary rows and columns zero.  gamma <= 0 selects k(k+1). */
+c0ip_status c0ip_host_matrices_1d(int degree, int n_cells, double gamma, double* M, double* L, double* B);
+/* The fast-diagonalisation inverse (eq. inverse) of the separable patch
+ * matrix of eq. localsolverbila for the vertex with multi-index
+ * vertex[0..dim-1] in [1, N-1], as a dense host array of (2k-1)^(2 dim)
+ * row-major entries (patch DoFs in lexicographic order, x fastest). */
+c0ip_status c0ip_host_patch_inverse(int dim, int degree, int n_cells, double gamma, const int* vertex,
+                                    double* Ainv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* C0IP_H */

@@ -46,7 +46,7 @@ __all__ = [
     "boundary_mask", "assemble", "Window", "patch_vertices", "patch_indices",
     "patch_blocks", "avs_apply", "prolongation_1d", "prolongation", "Hierarchy",
     "fgmres", "fractional_iterations", "load_vector", "manufactured_rhs", "energy_error",
-    "exact_solution_nodal",
+    "exact_solution_nodal", "window_around", "apply_rows_windowed", "avs_nodes_windowed",
 ]
 
 
@@ -382,6 +382,75 @@ def prolongation(dim: int, k: int, Nc: int) -> sp.csr_matrix:
     ff = (~boundary_mask(dim, k, 2 * Nc)).astype(np.float64)
     fc = (~boundary_mask(dim, k, Nc)).astype(np.float64)
     return (sp.diags(ff) @ P @ sp.diags(fc)).tocsr()
+
+
+# --------------------------------------------------------------------------
+# Sampled outputs at full size (windows of the mesh)
+# --------------------------------------------------------------------------
+
+def window_around(dim, k, N, node_multi, margin):
+    """Window of cells within ``margin`` cells of the cells containing the
+    node (clipped to the mesh)."""
+    lo, hi = [], []
+    for m in range(dim):
+        i = int(node_multi[m])
+        cmax = min(i // k, N - 1)
+        cmin = max(i // k - 1, 0) if i % k == 0 else i // k
+        lo.append(max(cmin - margin, 0))
+        hi.append(min(cmax + margin + 1, N))
+    return Window(dim, k, N, lo, hi)
+
+
+def _global_multi(dim, n1, g):
+    return np.array([(g // n1 ** m) % n1 for m in range(dim)])
+
+
+def apply_rows_windowed(dim, k, N, x, rows, gamma=None):
+    """(A x)[rows] for the full-size mesh, each row from the matrix assembled
+    on a window around it (rows of windows are exact, see Window.exact_rows)."""
+    n1 = k * N + 1
+    out = np.empty(len(rows))
+    for t, g in enumerate(rows):
+        gm = _global_multi(dim, n1, int(g))
+        win = window_around(dim, k, N, gm, 1)
+        A = assemble(dim, k, N, gamma, window=win)
+        li = int(win.local_of_global_multi(gm))
+        out[t] = float((A.getrow(li) @ x[win.gidx])[0])
+    return out
+
+
+def avs_nodes_windowed(dim, k, N, x, b, omega, nodes, gamma=None, x_is_zero=False):
+    """One additive smoothing step S(x, b) (or S(0, b)) evaluated at selected
+    nodes of the full-size mesh: residual, patch solves by dense LU and the
+    sum over the patches covering the node, on a window of cells around it."""
+    n1 = k * N + 1
+    out = np.empty(len(nodes))
+    for t, g in enumerate(nodes):
+        gm = _global_multi(dim, n1, int(g))
+        if np.any(gm == 0) or np.any(gm == n1 - 1):
+            out[t] = 0.0
+            continue
+        win = window_around(dim, k, N, gm, 3)
+        A = assemble(dim, k, N, gamma, window=win)
+        At = assemble(dim, k, N, gamma, bulk="diag", window=win)
+        xl = np.zeros(win.size) if x_is_zero else x[win.gidx] * win.free
+        r = b[win.gidx] * win.free - (A @ xl)
+        # vertices whose patch contains the node
+        cand = []
+        for m in range(dim):
+            i = int(gm[m])
+            cand.append([i // k] if i % k == 0 else [i // k, i // k + 1])
+        verts = np.array(np.meshgrid(*cand, indexing="ij")).reshape(dim, -1).T
+        verts = verts[np.all((verts >= 1) & (verts <= N - 1), axis=1)]
+        pidx = patch_indices(dim, k, N, verts, window=win)
+        blocks = patch_blocks(At, pidx)
+        li = int(win.local_of_global_multi(gm))
+        corr = 0.0
+        for p in range(len(verts)):
+            u = np.linalg.solve(blocks[p], r[pidx[p]])
+            corr += u[np.where(pidx[p] == li)[0][0]]
+        out[t] = (0.0 if x_is_zero else x[g]) + omega * corr
+    return out
 
 
 # --------------------------------------------------------------------------

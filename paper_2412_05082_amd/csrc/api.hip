@@ -1,0 +1,624 @@
+// C ABI of libc0ip: level hierarchy, V-cycle (Algorithm 1) and flexible
+// GMRES (Sec. 5.1-5.2) driving the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/c0ip.h"
+#include "kernels.h"
+#include "setup.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+c0ip_status fail(c0ip_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIP_TRY(expr)                                                \
+  do {                                                               \
+    hipError_t e_ = (expr);                                          \
+    if (e_ != hipSuccess) throw HipFail{e_, #expr};                  \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    HIP_TRY(hipMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T)));
+    n = count;
+  }
+  void upload(const std::vector<T>& v) {
+    alloc(v.size());
+    HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+// Device data and work space of one precision on one level.
+template <typename T>
+struct LevelWork {
+  DevBuf<T> tab, Q, lam, ptab;  // coefficient table, eigenbases, prolongation table
+  DevBuf<T> x, b, r, scratch;   // V-cycle vectors and transfer scratch
+  c0ip::LevelCoef<T> coef;
+  c0ip::LevelEig<T> eig;
+  bool ready = false;
+};
+
+struct Level {
+  int N = 0, n1 = 0;
+  int64_t ntot = 0;
+  c0ip::Level1D lv;
+  c0ip::RowClasses rc;
+  std::vector<double> tab, Q, lam;  // host copies (float64)
+  LevelWork<double> w64;
+  LevelWork<float> w32;
+};
+
+}  // namespace
+
+struct c0ip_problem {
+  int dim = 2, k = 2, N = 2, L = 0;
+  double gamma = 0;
+  c0ip_mg_opts mg{};
+  hipStream_t stream = nullptr;
+  std::vector<std::unique_ptr<Level>> lv;
+  std::vector<double> ptab;  // prolongation table (float64 host copy)
+  DevBuf<double> A0inv;
+  // Krylov work space
+  DevBuf<double> V, w, partial, hdev, ydev, r64;
+  DevBuf<double> Z64;
+  DevBuf<float> Z32;
+  DevBuf<int> nanflag;
+  int kry_m = 0;
+
+  int64_t ntot(int l) const { return lv[l]->ntot; }
+  template <typename T>
+  LevelWork<T>& work(int l);
+  template <typename T>
+  void prepare(int l);
+  template <typename T>
+  void smooth(int l, const T* b, T* x, int steps, bool x_is_zero);
+  template <typename T>
+  void mg_level(int l, const T* b, T* x);
+  void check(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw HipFail{e, what};
+  }
+};
+
+template <>
+LevelWork<double>& c0ip_problem::work<double>(int l) {
+  return lv[l]->w64;
+}
+template <>
+LevelWork<float>& c0ip_problem::work<float>(int l) {
+  return lv[l]->w32;
+}
+
+// Upload a level's tables in precision T and size its work vectors.
+template <typename T>
+void c0ip_problem::prepare(int l) {
+  LevelWork<T>& w = work<T>(l);
+  if (w.ready) return;
+  Level& L_ = *lv[l];
+  w.tab.upload(cast_vec<T>(L_.tab));
+  w.Q.upload(cast_vec<T>(L_.Q));
+  w.lam.upload(cast_vec<T>(L_.lam));
+  w.ptab.upload(cast_vec<T>(ptab));
+  w.coef.tab = w.tab.p;
+  w.coef.nclass = L_.rc.nclass;
+  w.coef.left = L_.rc.left;
+  w.coef.right0 = L_.rc.right0;
+  w.coef.periodic = L_.rc.periodic;
+  w.eig.Q = w.Q.p;
+  w.eig.lam = w.lam.p;
+  w.x.alloc(L_.ntot);
+  w.b.alloc(L_.ntot);
+  w.r.alloc(L_.ntot);
+  if (l > 0) {
+    const int64_t nf = L_.n1, nc = lv[l - 1]->n1;
+    const int64_t s = dim == 2 ? nf * nc : 2 * nf * nf * nc;
+    w.scratch.alloc(s);
+  }
+  w.ready = true;
+}
+
+// steps of the additive smoother on level l (x_is_zero: start from 0).
+template <typename T>
+void c0ip_problem::smooth(int l, const T* b, T* x, int steps, bool x_is_zero) {
+  LevelWork<T>& w = work<T>(l);
+  const int Nl = lv[l]->N;
+  const T om = (T)mg.omega;
+  if (steps <= 0) {
+    if (x_is_zero) check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), x, stream), "fill");
+    return;
+  }
+  for (int s = 0; s < steps; ++s) {
+    if (s == 0 && x_is_zero) {
+      check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, b, nullptr, x, om, stream), "smoother");
+    } else {
+      check(c0ip::launch_apply<T, T>(dim, k, Nl, w.coef, x, b, w.r.p, stream), "residual");
+      check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, w.r.p, x, x, om, stream), "smoother");
+    }
+  }
+}
+
+// x = MG_l(0, b) (Algorithm 1, returning right after the coarse solve).
+template <typename T>
+void c0ip_problem::mg_level(int l, const T* b, T* x) {
+  if (l == 0) {
+    if (mg.coarse_mode == 0) {
+      check(c0ip::launch_coarse<T>(dim, k, A0inv.p, b, x, stream), "coarse solve");
+    } else {
+      LevelWork<T>& w = work<T>(0);
+      check(c0ip::launch_patch_smooth<T>(dim, k, lv[0]->N, w.eig, b, nullptr, x, T(1), stream), "coarse smooth");
+    }
+    return;
+  }
+  LevelWork<T>& w = work<T>(l);
+  LevelWork<T>& wc = work<T>(l - 1);
+  smooth<T>(l, b, x, mg.pre_steps, true);
+  check(c0ip::launch_apply<T, T>(dim, k, lv[l]->N, w.coef, x, b, w.r.p, stream), "residual");
+  check(c0ip::launch_restrict<T>(dim, k, lv[l - 1]->N, w.ptab.p, w.r.p, wc.b.p, w.scratch.p, stream), "restrict");
+  mg_level<T>(l - 1, wc.b.p, wc.x.p);
+  check(c0ip::launch_prolong_add<T>(dim, k, lv[l - 1]->N, w.ptab.p, wc.x.p, x, w.scratch.p, stream), "prolong");
+  smooth<T>(l, b, x, mg.post_steps, false);
+}
+
+namespace {
+
+bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+c0ip_status hip_fail(const HipFail& h) {
+  return fail(C0IP_EHIP, std::string(h.what) + ": " + hipGetErrorString(h.e));
+}
+
+c0ip_status check_mesh(const c0ip_mesh_desc* m) {
+  if (!m) return fail(C0IP_EINVAL, "mesh descriptor is NULL");
+  if (m->dim != 2 && m->dim != 3) return fail(C0IP_EINVAL, "dim must be 2 or 3");
+  if (m->degree < 2 || m->degree > 7) return fail(C0IP_EINVAL, "degree must be in [2,7]");
+  if (!is_pow2(m->n_cells)) return fail(C0IP_EINVAL, "n_cells must be a power of two >= 2");
+  if (m->n_cells > (1 << 16)) return fail(C0IP_EINVAL, "n_cells too large");
+  return C0IP_OK;
+}
+
+int resolve_level(const c0ip_problem* p, int level) { return level < 0 ? p->L : level; }
+
+}  // namespace
+
+extern "C" {
+
+const char* c0ip_last_error(void) { return g_err.c_str(); }
+
+c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, void* hip_stream,
+                        c0ip_problem** out) {
+  g_err.clear();
+  if (!out) return fail(C0IP_EINVAL, "out is NULL");
+  *out = nullptr;
+  c0ip_status st = check_mesh(mesh);
+  if (st != C0IP_OK) return st;
+  c0ip_mg_opts mg;
+  if (opts) {
+    mg = *opts;
+  } else {
+    mg.omega = mesh->dim == 2 ? 0.25 : 0.1;
+    mg.pre_steps = mg.post_steps = 1;
+    mg.vcycle_dtype = C0IP_F32;
+    mg.coarse_mode = 0;
+    mg.scatter_mode = 0;
+  }
+  if (!(mg.omega > 0) || !std::isfinite(mg.omega)) return fail(C0IP_EINVAL, "omega must be > 0");
+  if (mg.pre_steps < 0 || mg.post_steps < 0 || mg.pre_steps > 16 || mg.post_steps > 16)
+    return fail(C0IP_EINVAL, "smoothing steps must be in [0,16]");
+  if (mg.vcycle_dtype != C0IP_F64 && mg.vcycle_dtype != C0IP_F32) return fail(C0IP_EINVAL, "bad vcycle_dtype");
+  if (mg.coarse_mode != 0 && mg.coarse_mode != 1) return fail(C0IP_EINVAL, "coarse_mode must be 0 or 1");
+  if (mg.scatter_mode != 0) return fail(C0IP_EUNSUPPORTED, "only scatter_mode 0 (owner-computes) is built");
+  std::unique_ptr<c0ip_problem> p(new c0ip_problem());
+  p->dim = mesh->dim;
+  p->k = mesh->degree;
+  p->N = mesh->n_cells;
+  p->gamma = mesh->gamma > 0 ? mesh->gamma : (double)(p->k * (p->k + 1));
+  p->mg = mg;
+  p->stream = (hipStream_t)hip_stream;
+  int L = 0;
+  while ((2 << L) < p->N) ++L;
+  p->L = L;
+  try {
+    p->ptab = c0ip::prolongation_table(p->k);
+    for (int l = 0; l <= L; ++l) {
+      std::unique_ptr<Level> lv(new Level());
+      lv->N = 2 << l;
+      lv->n1 = p->k * lv->N + 1;
+      lv->ntot = (int64_t)lv->n1 * lv->n1 * (p->dim == 3 ? lv->n1 : 1);
+      lv->lv = c0ip::build_level_1d(p->k, lv->N, p->gamma);
+      lv->rc = c0ip::row_classes(lv->lv);
+      lv->tab = c0ip::coefficient_table(lv->lv, lv->rc);
+      // every row must equal its class representative
+      {
+        const int kk = p->k, W = 4 * kk + 1;
+        const c0ip::Band* mats[3] = {&lv->lv.M, &lv->lv.L, &lv->lv.B};
+        for (int m = 0; m < 3; ++m) {
+          double mx = 0;
+          for (double v : mats[m]->a) mx = std::max(mx, std::fabs(v));
+          for (int i = 0; i < lv->n1; ++i) {
+            int cls;
+            if (!lv->rc.periodic || i < lv->rc.left) cls = i;
+            else if (i >= lv->rc.right0) cls = lv->rc.left + (lv->n1 - 1 - i);
+            else cls = 2 * lv->rc.left + i % kk;
+            for (int o = -2 * kk; o <= 2 * kk; ++o) {
+              int j = i + o;
+              double a = (j >= 0 && j < lv->n1) ? mats[m]->get(i, j) : 0.0;
+              double t = lv->tab[((size_t)m * lv->rc.nclass + cls) * W + (o + 2 * kk)];
+              if (std::fabs(a - t) > 1e-12 * mx) return fail(C0IP_EINVAL, "1D band is not periodic");
+            }
+          }
+        }
+      }
+      c0ip::PatchEigen pe;
+      std::string err;
+      if (!c0ip::build_patch_eigen(lv->lv, pe, err)) return fail(C0IP_EINVAL, err);
+      const int n = pe.n;
+      lv->Q.assign((size_t)4 * n * n, 0.0);
+      lv->lam.assign((size_t)4 * n, 1.0);
+      for (int t = 0; t < 4; ++t)
+        if (pe.present[t]) {
+          std::copy(pe.Q[t].begin(), pe.Q[t].end(), lv->Q.begin() + (size_t)t * n * n);
+          std::copy(pe.lam[t].begin(), pe.lam[t].end(), lv->lam.begin() + (size_t)t * n);
+        }
+      p->lv.push_back(std::move(lv));
+    }
+    std::vector<double> Ainv;
+    std::string err;
+    if (!c0ip::coarse_inverse(p->lv[0]->lv, p->dim, Ainv, err)) return fail(C0IP_EINVAL, err);
+    p->A0inv.upload(Ainv);
+    for (int l = 0; l <= L; ++l) p->prepare<double>(l);
+    if (p->mg.vcycle_dtype == C0IP_F32)
+      for (int l = 0; l <= L; ++l) p->prepare<float>(l);
+  } catch (const HipFail& h) {
+    return hip_fail(h);
+  } catch (const std::bad_alloc&) {
+    return fail(C0IP_ENOMEM, "host allocation failed");
+  }
+  *out = p.release();
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_destroy(c0ip_problem* p) {
+  g_err.clear();
+  delete p;
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_num_levels(const c0ip_problem* p, int* n_levels) {
+  if (!p || !n_levels) return fail(C0IP_EINVAL, "NULL argument");
+  *n_levels = p->L + 1;
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_num_dofs(const c0ip_problem* p, int level, int64_t* n_total) {
+  if (!p || !n_total) return fail(C0IP_EINVAL, "NULL argument");
+  if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
+  *n_total = p->ntot(resolve_level(p, level));
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_apply_A(c0ip_problem* p, int level, c0ip_dtype dtype, const void* x, void* y) {
+  g_err.clear();
+  if (!p || !x || !y) return fail(C0IP_EINVAL, "NULL argument");
+  if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
+  if (x == y) return fail(C0IP_EINVAL, "x and y must not overlap");
+  const int l = resolve_level(p, level);
+  try {
+    if (dtype == C0IP_F64) {
+      p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->lv[l]->N, p->work<double>(l).coef,
+                                                  (const double*)x, nullptr, (double*)y, p->stream),
+               "apply_A");
+    } else if (dtype == C0IP_F32) {
+      p->prepare<float>(l);
+      p->check(c0ip::launch_apply<float, float>(p->dim, p->k, p->lv[l]->N, p->work<float>(l).coef,
+                                                (const float*)x, nullptr, (float*)y, p->stream),
+               "apply_A");
+    } else {
+      return fail(C0IP_EINVAL, "bad dtype");
+    }
+  } catch (const HipFail& h) {
+    return hip_fail(h);
+  }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_apply_smoother(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b, void* x,
+                                int x_is_zero) {
+  g_err.clear();
+  if (!p || !b || !x) return fail(C0IP_EINVAL, "NULL argument");
+  if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
+  if (b == x) return fail(C0IP_EINVAL, "b and x must not overlap");
+  const int l = resolve_level(p, level);
+  try {
+    if (dtype == C0IP_F64) {
+      p->smooth<double>(l, (const double*)b, (double*)x, 1, x_is_zero != 0);
+    } else if (dtype == C0IP_F32) {
+      p->prepare<float>(l);
+      p->smooth<float>(l, (const float*)b, (float*)x, 1, x_is_zero != 0);
+    } else {
+      return fail(C0IP_EINVAL, "bad dtype");
+    }
+  } catch (const HipFail& h) {
+    return hip_fail(h);
+  }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_vcycle(c0ip_problem* p, c0ip_dtype dtype, const void* b, void* x) {
+  g_err.clear();
+  if (!p || !b || !x) return fail(C0IP_EINVAL, "NULL argument");
+  if (b == x) return fail(C0IP_EINVAL, "b and x must not overlap");
+  try {
+    if (dtype == C0IP_F64) {
+      p->mg_level<double>(p->L, (const double*)b, (double*)x);
+    } else if (dtype == C0IP_F32) {
+      for (int l = 0; l <= p->L; ++l) p->prepare<float>(l);
+      p->mg_level<float>(p->L, (const float*)b, (float*)x);
+    } else {
+      return fail(C0IP_EINVAL, "bad dtype");
+    }
+  } catch (const HipFail& h) {
+    return hip_fail(h);
+  }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const double* b, double* x,
+                       c0ip_solve_info* info) {
+  g_err.clear();
+  if (!p || !opts || !b || !x) return fail(C0IP_EINVAL, "NULL argument");
+  if (!(opts->rtol > 0) || opts->max_iters < 1 || opts->restart < 1 || opts->restart > 64)
+    return fail(C0IP_EINVAL, "bad Krylov options (rtol > 0, max_iters >= 1, restart in [1,64])");
+  if (b == x) return fail(C0IP_EINVAL, "b and x must not overlap");
+  const int m = opts->restart, Lf = p->L;
+  const int64_t n = p->ntot(Lf);
+  const bool f32 = p->mg.vcycle_dtype == C0IP_F32;
+  hipStream_t s = p->stream;
+  c0ip_solve_info inf{};
+  auto t0 = std::chrono::steady_clock::now();
+  double t_vc = 0, t_ar = 0;
+  c0ip_status result = C0IP_OK;
+  try {
+    const int nblk = c0ip::multidot_blocks(n);
+    p->V.alloc((size_t)(m + 1) * n);
+    p->w.alloc(n);
+    p->r64.alloc(n);
+    p->partial.alloc((size_t)(2 * m + 3) * nblk);
+    p->hdev.alloc(2 * m + 3);
+    p->ydev.alloc(m);
+    p->nanflag.alloc(1);
+    if (f32) {
+      p->Z32.alloc((size_t)m * n);
+      for (int l = 0; l <= Lf; ++l) p->prepare<float>(l);
+    } else {
+      p->Z64.alloc((size_t)m * n);
+    }
+    hipEvent_t e0, e1;
+    p->check(hipEventCreate(&e0), "event");
+    p->check(hipEventCreate(&e1), "event");
+    std::vector<double> hh(2 * m + 3);
+    auto dots = [&](int cnt, const double* Vp, const double* wp, int off) {
+      p->check(c0ip::launch_multidot(n, cnt, Vp, n, wp, p->partial.p, nblk, s), "multidot");
+      p->check(c0ip::launch_reduce_partials(cnt, nblk, p->partial.p, p->hdev.p + off, 0, s), "reduce");
+    };
+    auto fetch = [&](int cnt) {
+      p->check(hipMemcpyAsync(hh.data(), p->hdev.p, cnt * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+      p->check(hipStreamSynchronize(s), "sync");
+    };
+    const auto& cf64 = p->work<double>(Lf).coef;
+    // ||b|| over the free DoFs (boundary entries of b are ignored): r = b - A 0
+    p->check(c0ip::launch_fill(n, 0.0, p->w.p, s), "fill");
+    p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, p->w.p, b, p->r64.p, s), "mask b");
+    dots(1, p->r64.p, p->r64.p, 0);
+    fetch(1);
+    const double bnorm = std::sqrt(hh[0]);
+    if (!std::isfinite(bnorm)) throw c0ip_status(C0IP_ENAN);
+    // r = b - A x0
+    if (opts->x0_is_zero) {
+      p->check(c0ip::launch_fill(n, 0.0, x, s), "fill");
+    } else {
+      p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, x, b, p->r64.p, s), "residual");
+    }
+    dots(1, p->r64.p, p->r64.p, 0);
+    fetch(1);
+    double beta = std::sqrt(hh[0]);
+    std::vector<double> hist;
+    hist.push_back(beta);
+    int its = 0;
+    bool converged = bnorm == 0.0 || beta <= opts->rtol * bnorm;
+    if (bnorm == 0.0) p->check(c0ip::launch_fill(n, 0.0, x, s), "fill");
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    while (!converged && its < opts->max_iters) {
+      if (!(beta > 0) || !std::isfinite(beta)) throw c0ip_status(C0IP_ENAN);
+      // V_0 = r / beta
+      dots(1, p->r64.p, p->r64.p, 0);
+      p->check(c0ip::launch_normalize(n, p->r64.p, p->hdev.p, p->V.p, s), "normalize");
+      std::fill(H.begin(), H.end(), 0.0);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int jdone = 0;
+      bool stop = false;
+      for (int j = 0; j < m && !stop; ++j) {
+        double* Vj = p->V.p + (size_t)j * n;
+        p->check(hipEventRecord(e0, s), "event");
+        if (f32) {
+          float* Zj = p->Z32.p + (size_t)j * n;
+          LevelWork<float>& wf = p->work<float>(Lf);
+          p->check(c0ip::launch_cast<double, float>(n, Vj, wf.b.p, s), "cast");
+          p->mg_level<float>(Lf, wf.b.p, Zj);
+          p->check(hipEventRecord(e1, s), "event");
+          p->check(c0ip::launch_apply<float, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
+        } else {
+          double* Zj = p->Z64.p + (size_t)j * n;
+          p->mg_level<double>(Lf, Vj, Zj);
+          p->check(hipEventRecord(e1, s), "event");
+          p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
+        }
+        // classical Gram-Schmidt, twice
+        dots(j + 1, p->V.p, p->w.p, 0);
+        p->check(c0ip::launch_multiaxpy(n, j + 1, p->V.p, n, p->hdev.p, p->w.p, s), "axpy");
+        dots(j + 1, p->V.p, p->w.p, j + 1);
+        p->check(c0ip::launch_multiaxpy(n, j + 1, p->V.p, n, p->hdev.p + j + 1, p->w.p, s), "axpy");
+        dots(1, p->w.p, p->w.p, 2 * j + 2);
+        fetch(2 * j + 3);
+        float ms = 0;
+        p->check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        t_vc += ms * 1e-3;
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[j + 1 + i];
+        const double hn = std::sqrt(std::max(hh[2 * j + 2], 0.0));
+        if (!std::isfinite(hn)) throw c0ip_status(C0IP_ENAN);
+        H[(size_t)(j + 1) * m + j] = hn;
+        for (int i = 0; i < j; ++i) {
+          double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+          H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+          H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+        }
+        double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+        double den = std::hypot(a, bb);
+        cs[j] = a / den;
+        sn[j] = bb / den;
+        H[(size_t)j * m + j] = den;
+        H[(size_t)(j + 1) * m + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++its;
+        jdone = j + 1;
+        hist.push_back(std::fabs(g[j + 1]));
+        if (std::fabs(g[j + 1]) <= opts->rtol * bnorm || hn == 0.0 || its >= opts->max_iters) {
+          stop = true;
+        } else {
+          p->check(c0ip::launch_normalize(n, p->w.p, p->hdev.p + 2 * j + 2, p->V.p + (size_t)(j + 1) * n, s),
+                   "normalize");
+        }
+      }
+      // y = H^{-1} g, x += Z y
+      for (int i = jdone - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int l2 = i + 1; l2 < jdone; ++l2) t -= H[(size_t)i * m + l2] * y[l2];
+        y[i] = t / H[(size_t)i * m + i];
+      }
+      p->check(hipMemcpyAsync(p->ydev.p, y.data(), jdone * sizeof(double), hipMemcpyHostToDevice, s), "H2D");
+      if (f32)
+        p->check(c0ip::launch_update_solution<float>(n, jdone, p->Z32.p, n, p->ydev.p, x, s), "update");
+      else
+        p->check(c0ip::launch_update_solution<double>(n, jdone, p->Z64.p, n, p->ydev.p, x, s), "update");
+      p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, x, b, p->r64.p, s), "residual");
+      dots(1, p->r64.p, p->r64.p, 0);
+      fetch(1);
+      beta = std::sqrt(hh[0]);
+      converged = hist.back() <= opts->rtol * bnorm;
+    }
+    p->check(hipStreamSynchronize(s), "sync");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    inf.iterations = its;
+    inf.converged = converged ? 1 : 0;
+    inf.rel_res_est = bnorm > 0 ? hist.back() / bnorm : 0.0;
+    inf.rel_res_true = bnorm > 0 ? beta / bnorm : 0.0;
+    inf.frac_iters = (its > 0 && inf.rel_res_est > 0) ? 8.0 * its / (-std::log10(inf.rel_res_est)) : 0.0;
+    if (!std::isfinite(beta)) result = fail(C0IP_ENAN, "non-finite residual");
+    else if (!converged) result = fail(C0IP_NOT_CONVERGED, "max_iters reached");
+  } catch (const HipFail& h) {
+    result = hip_fail(h);
+  } catch (c0ip_status st) {
+    (void)hipStreamSynchronize(s);
+    result = fail(st, "non-finite value in the Krylov iteration");
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  inf.seconds_total = std::chrono::duration<double>(t1 - t0).count();
+  inf.seconds_vcycle = t_vc;
+  inf.seconds_arnoldi = std::max(0.0, inf.seconds_total - t_vc);
+  (void)t_ar;
+  if (info) *info = inf;
+  return result;
+}
+
+c0ip_status c0ip_host_matrices_1d(int degree, int n_cells, double gamma, double* M, double* L, double* B) {
+  g_err.clear();
+  if (degree < 2 || degree > 7 || n_cells < 1 || !M || !L || !B) return fail(C0IP_EINVAL, "bad argument");
+  const double gam = gamma > 0 ? gamma : (double)(degree * (degree + 1));
+  c0ip::Level1D lv = c0ip::build_level_1d(degree, n_cells, gam);
+  const int n1 = lv.n1;
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      M[(size_t)i * n1 + j] = lv.M.get(i, j);
+      L[(size_t)i * n1 + j] = lv.L.get(i, j);
+      B[(size_t)i * n1 + j] = lv.B.get(i, j);
+    }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_host_patch_inverse(int dim, int degree, int n_cells, double gamma, const int* vertex,
+                                    double* Ainv) {
+  g_err.clear();
+  if ((dim != 2 && dim != 3) || degree < 2 || degree > 7 || !is_pow2(n_cells) || !vertex || !Ainv)
+    return fail(C0IP_EINVAL, "bad argument");
+  for (int d = 0; d < dim; ++d)
+    if (vertex[d] < 1 || vertex[d] > n_cells - 1) return fail(C0IP_EINVAL, "vertex out of range");
+  const double gam = gamma > 0 ? gamma : (double)(degree * (degree + 1));
+  c0ip::Level1D lv = c0ip::build_level_1d(degree, n_cells, gam);
+  c0ip::PatchEigen pe;
+  std::string err;
+  if (!c0ip::build_patch_eigen(lv, pe, err)) return fail(C0IP_EINVAL, err);
+  const int n = pe.n;
+  int np = 1;
+  for (int d = 0; d < dim; ++d) np *= n;
+  const std::vector<double>* Q[3];
+  const std::vector<double>* lam[3];
+  for (int d = 0; d < dim; ++d) {
+    int t = c0ip::patch_variant(vertex[d], n_cells);
+    Q[d] = &pe.Q[t];
+    lam[d] = &pe.lam[t];
+  }
+  // Ainv = (Q_z (x) Q_y (x) Q_x) D^{-1} (...)^T, entry (r, c)
+  for (int r = 0; r < np; ++r)
+    for (int c = 0; c < np; ++c) {
+      int ri[3] = {r % n, (r / n) % n, r / (n * n)}, ci[3] = {c % n, (c / n) % n, c / (n * n)};
+      double s = 0;
+      for (int e = 0; e < np; ++e) {
+        int ei[3] = {e % n, (e / n) % n, e / (n * n)};
+        double qr = 1, qc = 1, lsum = 0;
+        for (int d = 0; d < dim; ++d) {
+          qr *= (*Q[d])[ri[d] * n + ei[d]];
+          qc *= (*Q[d])[ci[d] * n + ei[d]];
+          lsum += (*lam[d])[ei[d]];
+        }
+        s += qr * qc / lsum;
+      }
+      Ainv[(size_t)r * np + c] = s;
+    }
+  return C0IP_OK;
+}
+
+}  // extern "C"

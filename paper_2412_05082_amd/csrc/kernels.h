@@ -1,0 +1,97 @@
+// Launchers of the gfx950 kernels (internal to libc0ip; plain pointers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace c0ip {
+
+// Coefficient tables of one level's 1D M, L, B (row classes, see setup.h).
+template <typename T>
+struct LevelCoef {
+  const T* tab = nullptr;  // [3][nclass][4k+1]
+  int nclass = 0, left = 0, right0 = 0, periodic = 0;
+};
+
+// Fast-diagonalisation data of one level: Q[4][n*n], lam[4][n].
+template <typename T>
+struct LevelEig {
+  const T* Q = nullptr;
+  const T* lam = nullptr;
+};
+
+// y = A x, or y = b - A x when b != nullptr (boundary entries of y are 0).
+// Tin = type of x, T = compute/output type.
+template <typename Tin, typename T>
+hipError_t launch_apply(int dim, int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y,
+                        hipStream_t s);
+
+// x_out = x_in + omega * sum_v R_v^T A~_v^{-1} R_v r  (x_in == nullptr: 0).
+template <typename T>
+hipError_t launch_patch_smooth(int dim, int k, int N, const LevelEig<T>& e, const T* r, const T* x_in,
+                               T* x_out, T omega, hipStream_t s);
+
+// Grid transfers (tensor-product 1D embedding, table [2][k][k+1]).
+// restrict: bc = P^T rf;  prolong: xf (+)= P ec.  scratch >= n1f^(dim-1) * n1c elements.
+template <typename T>
+hipError_t launch_restrict(int dim, int k, int Nc, const T* table, const T* rf, T* bc, T* scratch,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(int dim, int k, int Nc, const T* table, const T* ec, T* xf, T* scratch,
+                              hipStream_t s);
+
+// Level-0 solve: x = A0^{-1} b on the (2k-1)^dim interior nodes (float64).
+template <typename T>
+hipError_t launch_coarse(int dim, int k, const double* Ainv, const T* b, T* x, hipStream_t s);
+
+// Vector kernels (n = length).
+template <typename Ta, typename Tb>
+hipError_t launch_cast(int64_t n, const Ta* a, Tb* b, hipStream_t s);
+hipError_t launch_fill(int64_t n, double v, double* a, hipStream_t s);
+template <typename T>
+hipError_t launch_fill_t(int64_t n, T v, T* a, hipStream_t s);
+// partial[j * nblk + blk] = partial sum of V_j . w (j < m), nblk blocks.
+hipError_t launch_multidot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* partial,
+                           int nblk, hipStream_t s);
+// out[j] = sum_b partial[j * nblk + b] (+ out_add[j] if accumulate)
+hipError_t launch_reduce_partials(int m, int nblk, const double* partial, double* out, int accumulate,
+                                  hipStream_t s);
+// w -= sum_j h[j] V_j   (h on the device)
+hipError_t launch_multiaxpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* w,
+                            hipStream_t s);
+// v = w / *nrm (nrm = device pointer to a squared norm: v = w / sqrt(*nrm))
+hipError_t launch_normalize(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t s);
+// x += sum_j y[j] Z_j  (Z of type Tz)
+template <typename Tz>
+hipError_t launch_update_solution(int64_t n, int m, const Tz* Z, int64_t ldz, const double* y, double* x,
+                                  hipStream_t s);
+// flags[0] |= any non-finite in a
+hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s);
+
+int multidot_blocks(int64_t n);
+
+// Per-dimension operator and smoother launchers (k dispatched at run time).
+template <typename Tin, typename T>
+hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s);
+template <typename T>
+hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
+                          hipStream_t s);
+template <typename Tin, typename T>
+hipError_t launch_apply3d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s);
+template <typename T>
+hipError_t launch_patch3d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
+                          hipStream_t s);
+
+#define C0IP_DISPATCH_K(k, CALL)          \
+  switch (k) {                            \
+    case 2: return CALL(2);               \
+    case 3: return CALL(3);               \
+    case 4: return CALL(4);               \
+    case 5: return CALL(5);               \
+    case 6: return CALL(6);               \
+    case 7: return CALL(7);               \
+    default: return hipErrorInvalidValue; \
+  }
+
+}  // namespace c0ip

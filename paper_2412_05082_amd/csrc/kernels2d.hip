@@ -1,0 +1,345 @@
+// 2D kernels: matrix-free C0IP operator and the additive vertex-patch
+// smoother with fast-diagonalisation local solves, for gfx950.
+//
+// Operator (Sec. 4, eq. c0iptensorvp, used globally on the Cartesian mesh):
+//   A x = (B (x) M + 2 L (x) L + M (x) B) x,  first factor along x.
+// In matrix form with X[j][i] (i = x index, fastest):
+//   Y = M_y (X B_x) + 2 L_y (X L_x) + B_y (X M_x).
+// One workgroup owns a tile of TY x TX output nodes (whole cells, so a
+// node's position in its cell is its tile-local index mod k).  It stages
+// X on the tile plus a 2k-node halo in LDS, runs the three x-sweeps into
+// LDS (X M_x on the 2k halo rows, X L_x and X B_x on the k halo rows), then
+// the three y-sweeps straight to HBM.  Band coefficients depend only on the
+// node's position in its cell away from the boundary; interior tiles read
+// them with wave-uniform addresses (scalar loads).
+//
+// Smoother (Sec. 3 additive vertex-patch Schwarz; local solver of eq.
+// localsolverbila inverted by eq. inverse):
+//   x_out = x_in + omega * sum_v R_v^T (Q_y (x) Q_x) D_v^{-1} (Q_y (x) Q_x)^T R_v r.
+// Owner-computes: a workgroup owns a tile of TC x TC cells, solves the
+// (TC+1)^2 patches that touch it (neighbouring tiles solve shared patches
+// twice instead of racing on writes), and writes each owned DoF once.
+#include "kernels.h"
+
+namespace c0ip {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int row_class(int g, int n1, int k, int left, int right0, int periodic) {
+  if (!periodic) return g;
+  if (g < left) return g;
+  if (g >= right0) return left + (n1 - 1 - g);
+  return 2 * left + g % k;
+}
+
+// Structural band of a row at position p in its cell (p = 0: vertex node).
+// M and L: support of one (p > 0) or two (p = 0) cells; B: one more cell
+// on each side through the point terms.
+template <int K> __host__ __device__ constexpr int m_lo(int p) { return p == 0 ? -K : -p; }
+template <int K> __host__ __device__ constexpr int m_hi(int p) { return p == 0 ? K : K - p; }
+template <int K> __host__ __device__ constexpr int b_lo(int p) { return p == 0 ? -2 * K : -K - p; }
+template <int K> __host__ __device__ constexpr int b_hi(int p) { return p == 0 ? 2 * K : 2 * K - p; }
+
+// ------------------------------------------------------------------ operator
+
+template <typename T, int K, int TXC, int TYC, bool INTERIOR>
+__device__ __forceinline__ void x_sweeps(const T* __restrict__ sX, T* __restrict__ sU, T* __restrict__ sV,
+                                         T* __restrict__ sW, int x0, int n1, const T* __restrict__ tab,
+                                         int nclass, int left, int right0, int periodic) {
+  constexpr int H = 2 * K, TX = TXC * K, TY = TYC * K, RX = TX + 2 * H, RY = TY + 2 * H, W = 4 * K + 1;
+  for (int it = threadIdx.x; it < RY * TXC; it += kThreads) {
+    const int r = it / TXC, cc = it - r * TXC;
+    T in[4 * K + 1];
+#pragma unroll
+    for (int j = 0; j <= 4 * K; ++j) in[j] = sX[r * RX + cc * K + j];
+    const bool vw = (r >= K) && (r < RY - K);
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      const int g = min(x0 + cc * K + p, n1 - 1);
+      const int cls = INTERIOR ? (2 * left + p) : row_class(g, n1, K, left, right0, periodic);
+      const T* cM = tab + (size_t)cls * W + H;
+      const T* cL = tab + (size_t)(nclass + cls) * W + H;
+      const T* cB = tab + (size_t)(2 * nclass + cls) * W + H;
+      T u = 0;
+#pragma unroll
+      for (int o = m_lo<K>(p); o <= m_hi<K>(p); ++o) u += cM[o] * in[p + o + H];
+      sU[r * TX + cc * K + p] = u;
+      if (vw) {
+        T v = 0, w = 0;
+#pragma unroll
+        for (int o = m_lo<K>(p); o <= m_hi<K>(p); ++o) v += cL[o] * in[p + o + H];
+#pragma unroll
+        for (int o = b_lo<K>(p); o <= b_hi<K>(p); ++o) w += cB[o] * in[p + o + H];
+        sV[(r - K) * TX + cc * K + p] = v;
+        sW[(r - K) * TX + cc * K + p] = w;
+      }
+    }
+  }
+}
+
+template <typename T, int K, int TXC, int TYC, bool INTERIOR, bool RES>
+__device__ __forceinline__ void y_sweeps(const T* __restrict__ sU, const T* __restrict__ sV,
+                                         const T* __restrict__ sW, int x0, int y0, int n1,
+                                         const T* __restrict__ tab, int nclass, int left, int right0,
+                                         int periodic, const T* __restrict__ b, T* __restrict__ y) {
+  constexpr int H = 2 * K, TX = TXC * K, W = 4 * K + 1;
+  for (int it = threadIdx.x; it < TX * TYC; it += kThreads) {
+    const int cr = it / TX, l = it - cr * TX;
+    const int gx = x0 + l;
+    if (gx >= n1) continue;
+    T u[4 * K + 1], v[2 * K + 1], w[2 * K + 1];
+#pragma unroll
+    for (int j = 0; j <= 4 * K; ++j) u[j] = sU[(cr * K + j) * TX + l];
+#pragma unroll
+    for (int j = 0; j <= 2 * K; ++j) {
+      v[j] = sV[(cr * K + j) * TX + l];
+      w[j] = sW[(cr * K + j) * TX + l];
+    }
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      const int gy = y0 + cr * K + p;
+      if (gy >= n1) break;
+      const int cls = INTERIOR ? (2 * left + p) : row_class(gy, n1, K, left, right0, periodic);
+      const T* cM = tab + (size_t)cls * W + H;
+      const T* cL = tab + (size_t)(nclass + cls) * W + H;
+      const T* cB = tab + (size_t)(2 * nclass + cls) * W + H;
+      T am = 0, al = 0, ab = 0;
+#pragma unroll
+      for (int o = m_lo<K>(p); o <= m_hi<K>(p); ++o) {
+        am += cM[o] * w[p + o + K];
+        al += cL[o] * v[p + o + K];
+      }
+#pragma unroll
+      for (int o = b_lo<K>(p); o <= b_hi<K>(p); ++o) ab += cB[o] * u[p + o + H];
+      const T acc = am + 2 * al + ab;
+      const size_t idx = (size_t)gy * n1 + gx;
+      if (RES) {
+        const bool bnd = (gx == 0) | (gx == n1 - 1) | (gy == 0) | (gy == n1 - 1);
+        y[idx] = bnd ? T(0) : (b[idx] - acc);
+      } else {
+        y[idx] = acc;
+      }
+    }
+  }
+}
+
+template <typename Tin, typename T, int K, int TXC, int TYC, bool RES>
+__global__ __launch_bounds__(kThreads) void apply2d_kernel(const Tin* __restrict__ x, const T* __restrict__ b,
+                                                           T* __restrict__ y, int n1, const T* __restrict__ tab,
+                                                           int nclass, int left, int right0, int periodic) {
+  constexpr int H = 2 * K, TX = TXC * K, TY = TYC * K, RX = TX + 2 * H, RY = TY + 2 * H;
+  __shared__ T sX[RY * RX];
+  __shared__ T sU[RY * TX];
+  __shared__ T sV[(TY + 2 * K) * TX];
+  __shared__ T sW[(TY + 2 * K) * TX];
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  for (int e = threadIdx.x; e < RY * RX; e += kThreads) {
+    const int r = e / RX, c = e - r * RX;
+    const int gy = y0 - H + r, gx = x0 - H + c;
+    T v = 0;
+    if (gy >= 0 && gy < n1 && gx >= 0 && gx < n1) v = (T)x[(size_t)gy * n1 + gx];
+    sX[e] = v;
+  }
+  __syncthreads();
+  const bool xin = periodic && x0 >= left && x0 + TX <= right0;
+  if (xin)
+    x_sweeps<T, K, TXC, TYC, true>(sX, sU, sV, sW, x0, n1, tab, nclass, left, right0, periodic);
+  else
+    x_sweeps<T, K, TXC, TYC, false>(sX, sU, sV, sW, x0, n1, tab, nclass, left, right0, periodic);
+  __syncthreads();
+  const bool yin = periodic && y0 >= left && y0 + TY <= right0;
+  if (yin)
+    y_sweeps<T, K, TXC, TYC, true, RES>(sU, sV, sW, x0, y0, n1, tab, nclass, left, right0, periodic, b, y);
+  else
+    y_sweeps<T, K, TXC, TYC, false, RES>(sU, sV, sW, x0, y0, n1, tab, nclass, left, right0, periodic, b, y);
+}
+
+template <int K> struct ApplyTile2D;
+template <> struct ApplyTile2D<2> { static constexpr int TXC = 16, TYC = 16; };
+template <> struct ApplyTile2D<3> { static constexpr int TXC = 16, TYC = 8; };
+template <> struct ApplyTile2D<4> { static constexpr int TXC = 8, TYC = 8; };
+template <> struct ApplyTile2D<5> { static constexpr int TXC = 8, TYC = 4; };
+template <> struct ApplyTile2D<6> { static constexpr int TXC = 4, TYC = 4; };
+template <> struct ApplyTile2D<7> { static constexpr int TXC = 4, TYC = 4; };
+
+template <typename Tin, typename T, int K>
+hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s) {
+  constexpr int TXC = ApplyTile2D<K>::TXC, TYC = ApplyTile2D<K>::TYC;
+  const int n1 = K * N + 1;
+  dim3 grid((n1 + TXC * K - 1) / (TXC * K), (n1 + TYC * K - 1) / (TYC * K));
+  if (b)
+    apply2d_kernel<Tin, T, K, TXC, TYC, true><<<grid, kThreads, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left,
+                                                                        c.right0, c.periodic);
+  else
+    apply2d_kernel<Tin, T, K, TXC, TYC, false><<<grid, kThreads, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left,
+                                                                         c.right0, c.periodic);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ smoother
+
+__device__ __forceinline__ int variant(int v, int N) { return (v == 1 ? 1 : 0) | (v == N - 1 ? 2 : 0); }
+
+template <typename T, int K, int TC>
+__global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__ r, const T* __restrict__ xin,
+                                                           T* __restrict__ xout, int N, int n1,
+                                                           const T* __restrict__ Q, const T* __restrict__ lam,
+                                                           T omega) {
+  constexpr int n = 2 * K - 1, NN = n * n, NP = TC + 1, S = (TC + 2) * K - 1;
+  __shared__ T sR[S * S];
+  __shared__ T sA[NP * NP * NN];
+  __shared__ T sB[NP * NP * NN];
+  const int cx0 = blockIdx.x * TC, cy0 = blockIdx.y * TC;
+  const int ox = (cx0 - 1) * K + 1, oy = (cy0 - 1) * K + 1;  // global node of region (0,0)
+  for (int e = threadIdx.x; e < S * S; e += kThreads) {
+    const int rr = e / S, cc = e - rr * S;
+    const int gy = oy + rr, gx = ox + cc;
+    T v = 0;
+    if (gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2) v = r[(size_t)gy * n1 + gx];
+    sR[e] = v;
+  }
+  __syncthreads();
+  // forward along x: t[a][c] = sum_c' Qx[c'][c] r[a][c']
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, a = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = cx0 + pxl, vy = cy0 + pyl;
+    if (vx < 1 || vx > N - 1 || vy < 1 || vy > N - 1) continue;
+    const T* q = Q + variant(vx, N) * NN;
+    T in[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) in[c] = sR[(pyl * K + a) * S + pxl * K + c];
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int cp = 0; cp < n; ++cp) s += q[cp * n + c] * in[cp];
+      sA[p * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  // along y: forward with Qy^T, divide by lambda_x + lambda_y, back with Qy
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, c = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = cx0 + pxl, vy = cy0 + pyl;
+    if (vx < 1 || vx > N - 1 || vy < 1 || vy > N - 1) continue;
+    const int ty = variant(vy, N), tx = variant(vx, N);
+    const T* q = Q + ty * NN;
+    const T lx = lam[tx * n + c];
+    T col[n], t[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) col[a] = sA[p * NN + a * n + c];
+#pragma unroll
+    for (int ap = 0; ap < n; ++ap) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) s += q[a * n + ap] * col[a];
+      t[ap] = s / (lx + lam[ty * n + ap]);
+    }
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int ap = 0; ap < n; ++ap) s += q[a * n + ap] * t[ap];
+      sB[p * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  // back along x: u[a][c'] = sum_c Qx[c'][c] t[a][c]
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, a = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = cx0 + pxl, vy = cy0 + pyl;
+    if (vx < 1 || vx > N - 1 || vy < 1 || vy > N - 1) continue;
+    const T* q = Q + variant(vx, N) * NN;
+    T in[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) in[c] = sB[p * NN + a * n + c];
+#pragma unroll
+    for (int cp = 0; cp < n; ++cp) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < n; ++c) s += q[cp * n + c] * in[c];
+      sA[p * NN + a * n + cp] = s;
+    }
+  }
+  __syncthreads();
+  // owned DoFs: sum the covering patches' corrections
+  constexpr int OW = TC * K + 1;
+  const int gx0 = cx0 * K, gy0 = cy0 * K;
+  const int gx1 = (cx0 + TC >= N) ? n1 : (cx0 + TC) * K;
+  const int gy1 = (cy0 + TC >= N) ? n1 : (cy0 + TC) * K;
+  for (int e = threadIdx.x; e < OW * OW; e += kThreads) {
+    const int jj = e / OW, ii = e - jj * OW;
+    const int gx = gx0 + ii, gy = gy0 + jj;
+    if (gx >= gx1 || gy >= gy1) continue;
+    const size_t idx = (size_t)gy * n1 + gx;
+    if (gx == 0 || gx == n1 - 1 || gy == 0 || gy == n1 - 1) {
+      xout[idx] = T(0);
+      continue;
+    }
+    const int vxa = gx / K, vxb = (gx % K == 0) ? vxa : vxa + 1;
+    const int vya = gy / K, vyb = (gy % K == 0) ? vya : vya + 1;
+    T acc = 0;
+    for (int vy = vya; vy <= vyb; ++vy) {
+      if (vy < 1 || vy > N - 1) continue;
+      for (int vx = vxa; vx <= vxb; ++vx) {
+        if (vx < 1 || vx > N - 1) continue;
+        const int p = (vy - cy0) * NP + (vx - cx0);
+        const int c = gx - ((vx - 1) * K + 1), a = gy - ((vy - 1) * K + 1);
+        acc += sA[p * NN + a * n + c];
+      }
+    }
+    xout[idx] = (xin ? xin[idx] : T(0)) + omega * acc;
+  }
+}
+
+template <int K> struct PatchTile2D;
+template <> struct PatchTile2D<2> { static constexpr int TC = 16; };
+template <> struct PatchTile2D<3> { static constexpr int TC = 8; };
+template <> struct PatchTile2D<4> { static constexpr int TC = 8; };
+template <> struct PatchTile2D<5> { static constexpr int TC = 4; };
+template <> struct PatchTile2D<6> { static constexpr int TC = 4; };
+template <> struct PatchTile2D<7> { static constexpr int TC = 4; };
+
+template <typename T, int K>
+hipError_t patch2d_k(int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega, hipStream_t s) {
+  constexpr int TC = PatchTile2D<K>::TC;
+  const int n1 = K * N + 1;
+  const int nt = (N + TC - 1) / TC;
+  dim3 grid(nt, nt);
+  patch2d_kernel<T, K, TC><<<grid, kThreads, 0, s>>>(r, xin, xout, N, n1, e.Q, e.lam, omega);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename Tin, typename T>
+hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s) {
+#define CALL(K) apply2d_k<Tin, T, K>(N, c, x, b, y, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template <typename T>
+hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
+                          hipStream_t s) {
+#define CALL(K) patch2d_k<T, K>(N, e, r, xin, xout, omega, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template hipError_t launch_apply2d<double, double>(int, int, const LevelCoef<double>&, const double*,
+                                                   const double*, double*, hipStream_t);
+template hipError_t launch_apply2d<float, double>(int, int, const LevelCoef<double>&, const float*,
+                                                  const double*, double*, hipStream_t);
+template hipError_t launch_apply2d<float, float>(int, int, const LevelCoef<float>&, const float*, const float*,
+                                                 float*, hipStream_t);
+template hipError_t launch_patch2d<double>(int, int, const LevelEig<double>&, const double*, const double*,
+                                           double*, double, hipStream_t);
+template hipError_t launch_patch2d<float>(int, int, const LevelEig<float>&, const float*, const float*, float*,
+                                          float, hipStream_t);
+
+}  // namespace c0ip

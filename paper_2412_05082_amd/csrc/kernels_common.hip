@@ -1,0 +1,396 @@
+// Dimension-independent kernels: grid transfers, the level-0 solve and the
+// Krylov vector kernels.
+//
+// Transfers (Sec. 3): prolongation = embedding of Q_k on the coarse mesh
+// into Q_k on the refined mesh, restriction = its transpose.  Both are
+// tensor products of one 1D matrix and are applied one axis at a time;
+// along an axis a vector is viewed as [outer][n_axis][inner].
+#include "kernels.h"
+
+namespace c0ip {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int grid_for(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b > (1 << 20)) b = 1 << 20;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// out[i_f] (+)= sum_a T[s][p][a] in[cc k + a],  fine node i_f = (2cc+s) k + p.
+template <typename T, int K, bool ACC>
+__global__ __launch_bounds__(kThreads) void prolong1d_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                             int64_t inner, int nin, int nout, int64_t outer,
+                                                             const T* __restrict__ tab) {
+  const int64_t total = inner * nout * outer;
+  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * kThreads) {
+    const int64_t ii = idx % inner, rest = idx / inner;
+    const int f = (int)(rest % nout);
+    const int64_t io = rest / nout;
+    T v = 0;
+    if (f > 0 && f < nout - 1) {
+      const int cf = f / K, p = f - cf * K, cc = cf >> 1, s = cf & 1;
+      const T* base = in + ii + inner * ((int64_t)cc * K + (int64_t)nin * io);
+      const T* tb = tab + (s * K + p) * (K + 1);
+#pragma unroll
+      for (int a = 0; a <= K; ++a) v += tb[a] * base[a * inner];
+    }
+    T* o = out + ii + inner * ((int64_t)f + (int64_t)nout * io);
+    if (ACC)
+      *o += v;
+    else
+      *o = v;
+  }
+}
+
+// out[I] = sum over fine nodes of P[i_f][I] in[i_f]; coarse node I = cc k + a.
+template <typename T, int K>
+__global__ __launch_bounds__(kThreads) void restrict1d_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                              int64_t inner, int nin, int nout, int64_t outer,
+                                                              const T* __restrict__ tab) {
+  const int64_t total = inner * nout * outer;
+  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * kThreads) {
+    const int64_t ii = idx % inner, rest = idx / inner;
+    const int I = (int)(rest % nout);
+    const int64_t io = rest / nout;
+    T v = 0;
+    if (I > 0 && I < nout - 1) {
+      const int cc = I / K, a = I - cc * K;
+      const T* base = in + ii + inner * ((int64_t)nin * io);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int p = 0; p < K; ++p)
+          v += tab[(s * K + p) * (K + 1) + a] * base[inner * ((int64_t)(2 * cc + s) * K + p)];
+      if (a == 0) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int p = 0; p < K; ++p)
+            v += tab[(s * K + p) * (K + 1) + K] * base[inner * ((int64_t)(2 * cc - 2 + s) * K + p)];
+      }
+    }
+    out[ii + inner * ((int64_t)I + (int64_t)nout * io)] = v;
+  }
+}
+
+template <typename T, int K>
+hipError_t restrict_k(int dim, int Nc, const T* tab, const T* rf, T* bc, T* scratch, hipStream_t s) {
+  const int64_t nf = (int64_t)K * 2 * Nc + 1, nc = (int64_t)K * Nc + 1;
+  // sizes along axes after each pass, x fastest
+  int64_t sz[3] = {nf, nf, dim == 3 ? nf : 1};
+  const T* src = rf;
+  T* bufs[2] = {scratch, scratch + (dim == 3 ? nf * nf * nc : 0)};
+  for (int ax = 0; ax < dim; ++ax) {
+    int64_t inner = 1, outer = 1;
+    for (int m = 0; m < ax; ++m) inner *= sz[m];
+    for (int m = ax + 1; m < dim; ++m) outer *= sz[m];
+    T* dst = (ax == dim - 1) ? bc : bufs[ax & 1];
+    const int64_t total = inner * nc * outer;
+    restrict1d_kernel<T, K><<<grid_for(total), kThreads, 0, s>>>(src, dst, inner, (int)nf, (int)nc, outer, tab);
+    sz[ax] = nc;
+    src = dst;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t prolong_k(int dim, int Nc, const T* tab, const T* ec, T* xf, T* scratch, hipStream_t s) {
+  const int64_t nf = (int64_t)K * 2 * Nc + 1, nc = (int64_t)K * Nc + 1;
+  int64_t sz[3] = {nc, nc, dim == 3 ? nc : 1};
+  const T* src = ec;
+  T* bufs[2] = {scratch, scratch + (dim == 3 ? nf * nf * nc : 0)};
+  for (int ax = 0; ax < dim; ++ax) {
+    int64_t inner = 1, outer = 1;
+    for (int m = 0; m < ax; ++m) inner *= sz[m];
+    for (int m = ax + 1; m < dim; ++m) outer *= sz[m];
+    const int64_t total = inner * nf * outer;
+    if (ax == dim - 1) {
+      prolong1d_kernel<T, K, true><<<grid_for(total), kThreads, 0, s>>>(src, xf, inner, (int)nc, (int)nf, outer,
+                                                                         tab);
+    } else {
+      T* dst = bufs[ax & 1];
+      prolong1d_kernel<T, K, false><<<grid_for(total), kThreads, 0, s>>>(src, dst, inner, (int)nc, (int)nf,
+                                                                          outer, tab);
+      src = dst;
+    }
+    sz[ax] = nf;
+  }
+  return hipGetLastError();
+}
+
+// Level 0: n1 = 2k+1 nodes per axis, interior nodes 1..2k-1; x = A0^{-1} b
+// on the interior, 0 on the boundary.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void coarse_kernel(int dim, int k, const double* __restrict__ Ainv,
+                                                          const T* __restrict__ b, T* __restrict__ x) {
+  const int n1 = 2 * k + 1, n = 2 * k - 1;
+  const int ntot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
+  const int n0 = dim == 2 ? n * n : n * n * n;
+  for (int g = blockIdx.x * kThreads + threadIdx.x; g < ntot; g += gridDim.x * kThreads) {
+    const int i0 = g % n1, i1 = (g / n1) % n1, i2 = dim == 3 ? g / (n1 * n1) : 1;
+    const bool interior = i0 >= 1 && i0 <= n && i1 >= 1 && i1 <= n && i2 >= 1 && i2 <= n;
+    double s = 0;
+    if (interior) {
+      const int row = (i0 - 1) + n * (i1 - 1) + (dim == 3 ? n * n * (i2 - 1) : 0);
+      for (int c = 0; c < n0; ++c) {
+        const int c0 = c % n + 1, c1 = (c / n) % n + 1, c2 = c / (n * n) + 1;
+        const int gc = c0 + n1 * c1 + (dim == 3 ? n1 * n1 * c2 : 0);
+        s += Ainv[(size_t)row * n0 + c] * (double)b[gc];
+      }
+    }
+    x[g] = (T)s;
+  }
+}
+
+template <typename Ta, typename Tb>
+__global__ __launch_bounds__(kThreads) void cast_kernel(int64_t n, const Ta* __restrict__ a, Tb* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    b[i] = (Tb)a[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void fill_kernel(int64_t n, T v, T* __restrict__ a) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    a[i] = v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Each block reduces a contiguous chunk against the m vectors, eight at a
+// time: every w element loaded feeds eight products.
+constexpr int kDotPerThread = 8;
+constexpr int kMaxDot = 64;
+constexpr int kDotGroup = 8;
+
+__global__ __launch_bounds__(kThreads) void multidot_kernel(int64_t n, int m, const double* __restrict__ V,
+                                                            int64_t ldv, const double* __restrict__ w,
+                                                            double* __restrict__ partial, int nblk) {
+  __shared__ double red[kThreads / 64][kDotGroup];
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < m; j0 += kDotGroup) {
+    double acc[kDotGroup];
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) acc[q] = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+      const double wi = w[i];
+#pragma unroll
+      for (int q = 0; q < kDotGroup; ++q)
+        if (j0 + q < m) acc[q] += V[(int64_t)(j0 + q) * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0) red[wid][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDotGroup && j0 + threadIdx.x < m) {
+      double s = 0;
+      for (int q = 0; q < kThreads / 64; ++q) s += red[q][threadIdx.x];
+      partial[(int64_t)(j0 + threadIdx.x) * nblk + blockIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_partials_kernel(int nblk, const double* __restrict__ partial,
+                                                                   double* __restrict__ out, int accumulate) {
+  __shared__ double red[kThreads / 64];
+  const int j = blockIdx.x;
+  double s = 0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) s += partial[(int64_t)j * nblk + b];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int q = 0; q < kThreads / 64; ++q) t += red[q];
+    out[j] = accumulate ? out[j] + t : t;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void multiaxpy_kernel(int64_t n, int m, const double* __restrict__ V,
+                                                             int64_t ldv, const double* __restrict__ h,
+                                                             double* __restrict__ w) {
+  __shared__ double sh[kMaxDot];
+  for (int j0 = 0; j0 < m; j0 += kMaxDot) {
+    const int mj = min(kMaxDot, m - j0);
+    __syncthreads();
+    if (threadIdx.x < mj) sh[threadIdx.x] = h[j0 + threadIdx.x];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+      double s = w[i];
+      for (int j = 0; j < mj; ++j) s -= sh[j] * V[(int64_t)(j0 + j) * ldv + i];
+      w[i] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void normalize_kernel(int64_t n, const double* __restrict__ w,
+                                                             const double* __restrict__ nrm2,
+                                                             double* __restrict__ v) {
+  const double inv = 1.0 / sqrt(nrm2[0]);
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    v[i] = w[i] * inv;
+}
+
+template <typename Tz>
+__global__ __launch_bounds__(kThreads) void update_solution_kernel(int64_t n, int m, const Tz* __restrict__ Z,
+                                                                   int64_t ldz, const double* __restrict__ y,
+                                                                   double* __restrict__ x) {
+  __shared__ double sy[kMaxDot];
+  for (int j0 = 0; j0 < m; j0 += kMaxDot) {
+    const int mj = min(kMaxDot, m - j0);
+    __syncthreads();
+    if (threadIdx.x < mj) sy[threadIdx.x] = y[j0 + threadIdx.x];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+      double s = x[i];
+      for (int j = 0; j < mj; ++j) s += sy[j] * (double)Z[(int64_t)(j0 + j) * ldz + i];
+      x[i] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void check_finite_kernel(int64_t n, const double* __restrict__ a,
+                                                                int* __restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    bad |= !isfinite(a[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+int multidot_blocks(int64_t n) {
+  int64_t b = (n + kThreads * kDotPerThread - 1) / (kThreads * kDotPerThread);
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename Tin, typename T>
+hipError_t launch_apply(int dim, int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y,
+                        hipStream_t s) {
+  return dim == 2 ? launch_apply2d<Tin, T>(k, N, c, x, b, y, s) : launch_apply3d<Tin, T>(k, N, c, x, b, y, s);
+}
+
+template <typename T>
+hipError_t launch_patch_smooth(int dim, int k, int N, const LevelEig<T>& e, const T* r, const T* x_in, T* x_out,
+                               T omega, hipStream_t s) {
+  return dim == 2 ? launch_patch2d<T>(k, N, e, r, x_in, x_out, omega, s)
+                  : launch_patch3d<T>(k, N, e, r, x_in, x_out, omega, s);
+}
+
+template <typename T>
+hipError_t launch_restrict(int dim, int k, int Nc, const T* table, const T* rf, T* bc, T* scratch, hipStream_t s) {
+#define CALL(K) restrict_k<T, K>(dim, Nc, table, rf, bc, scratch, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template <typename T>
+hipError_t launch_prolong_add(int dim, int k, int Nc, const T* table, const T* ec, T* xf, T* scratch,
+                              hipStream_t s) {
+#define CALL(K) prolong_k<T, K>(dim, Nc, table, ec, xf, scratch, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template <typename T>
+hipError_t launch_coarse(int dim, int k, const double* Ainv, const T* b, T* x, hipStream_t s) {
+  const int n1 = 2 * k + 1, ntot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
+  coarse_kernel<T><<<(ntot + kThreads - 1) / kThreads, kThreads, 0, s>>>(dim, k, Ainv, b, x);
+  return hipGetLastError();
+}
+
+template <typename Ta, typename Tb>
+hipError_t launch_cast(int64_t n, const Ta* a, Tb* b, hipStream_t s) {
+  cast_kernel<Ta, Tb><<<grid_for(n), kThreads, 0, s>>>(n, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t n, double v, double* a, hipStream_t s) {
+  fill_kernel<double><<<grid_for(n), kThreads, 0, s>>>(n, v, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_t(int64_t n, T v, T* a, hipStream_t s) {
+  fill_kernel<T><<<grid_for(n), kThreads, 0, s>>>(n, v, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_multidot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* partial,
+                           int nblk, hipStream_t s) {
+  multidot_kernel<<<nblk, kThreads, 0, s>>>(n, m, V, ldv, w, partial, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(int m, int nblk, const double* partial, double* out, int accumulate,
+                                  hipStream_t s) {
+  reduce_partials_kernel<<<m, kThreads, 0, s>>>(nblk, partial, out, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* w,
+                            hipStream_t s) {
+  multiaxpy_kernel<<<grid_for(n), kThreads, 0, s>>>(n, m, V, ldv, h, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t s) {
+  normalize_kernel<<<grid_for(n), kThreads, 0, s>>>(n, w, nrm2, v);
+  return hipGetLastError();
+}
+
+template <typename Tz>
+hipError_t launch_update_solution(int64_t n, int m, const Tz* Z, int64_t ldz, const double* y, double* x,
+                                  hipStream_t s) {
+  update_solution_kernel<Tz><<<grid_for(n), kThreads, 0, s>>>(n, m, Z, ldz, y, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s) {
+  check_finite_kernel<<<grid_for(n), kThreads, 0, s>>>(n, a, flag);
+  return hipGetLastError();
+}
+
+template hipError_t launch_apply<double, double>(int, int, int, const LevelCoef<double>&, const double*,
+                                                 const double*, double*, hipStream_t);
+template hipError_t launch_apply<float, double>(int, int, int, const LevelCoef<double>&, const float*,
+                                                const double*, double*, hipStream_t);
+template hipError_t launch_apply<float, float>(int, int, int, const LevelCoef<float>&, const float*, const float*,
+                                               float*, hipStream_t);
+template hipError_t launch_patch_smooth<double>(int, int, int, const LevelEig<double>&, const double*,
+                                                const double*, double*, double, hipStream_t);
+template hipError_t launch_patch_smooth<float>(int, int, int, const LevelEig<float>&, const float*, const float*,
+                                               float*, float, hipStream_t);
+template hipError_t launch_restrict<double>(int, int, int, const double*, const double*, double*, double*,
+                                            hipStream_t);
+template hipError_t launch_restrict<float>(int, int, int, const float*, const float*, float*, float*, hipStream_t);
+template hipError_t launch_prolong_add<double>(int, int, int, const double*, const double*, double*, double*,
+                                               hipStream_t);
+template hipError_t launch_prolong_add<float>(int, int, int, const float*, const float*, float*, float*,
+                                              hipStream_t);
+template hipError_t launch_coarse<double>(int, int, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_coarse<float>(int, int, const double*, const float*, float*, hipStream_t);
+template hipError_t launch_cast<double, float>(int64_t, const double*, float*, hipStream_t);
+template hipError_t launch_cast<float, double>(int64_t, const float*, double*, hipStream_t);
+template hipError_t launch_fill_t<float>(int64_t, float, float*, hipStream_t);
+template hipError_t launch_fill_t<double>(int64_t, double, double*, hipStream_t);
+template hipError_t launch_update_solution<double>(int64_t, int, const double*, int64_t, const double*, double*,
+                                                   hipStream_t);
+template hipError_t launch_update_solution<float>(int64_t, int, const float*, int64_t, const double*, double*,
+                                                  hipStream_t);
+
+}  // namespace c0ip

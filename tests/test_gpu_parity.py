@@ -1,0 +1,240 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: float64 results within 1e-12 relative l2 of the oracle;
+float32 smoother/operator applies within 1e-5 relative l2 of the float64
+oracle.  Sizes span several tiles and ragged last tiles; the full-size
+workloads (2D Q3 512^2 and the degree sweep) are checked on sampled
+outputs computed by the windowed oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2412_05082_amd as P
+from tests.gpu_util import dev, host, oracle_ops, rel_l2, say, vectors
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(2, 2, 16), (2, 2, 32), (2, 3, 8), (2, 3, 32), (2, 4, 16), (2, 5, 8), (2, 6, 8), (2, 7, 8), (2, 7, 16),
+         (2, 3, 2), (2, 5, 4)]
+
+
+def _problem(dim, k, N, **kw):
+    return P.Problem(dim, N, k, **kw)
+
+
+@pytest.mark.parametrize("dim,k,N", SMALL)
+def test_apply_A_f64_matches_oracle(dim, k, N):
+    say("apply_A f64", dim, k, N)
+    A, _, _ = oracle_ops(dim, k, N)
+    x, _ = vectors(dim, k, N)
+    x_in = x.copy()
+    x_in[O.boundary_mask(dim, k, N)] = 7.0  # boundary inputs are ignored
+    pb = _problem(dim, k, N)
+    y = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+    pb.apply_A(dev(x_in), y)
+    torch.cuda.synchronize()
+    assert rel_l2(host(y), A @ x) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 32), (2, 3, 32), (2, 5, 8), (2, 7, 16)])
+def test_apply_A_f32_matches_oracle(dim, k, N):
+    say("apply_A f32", dim, k, N)
+    A, _, _ = oracle_ops(dim, k, N)
+    x, _ = vectors(dim, k, N)
+    x32 = x.astype(np.float32)
+    pb = _problem(dim, k, N)
+    y = torch.empty(A.shape[0], dtype=torch.float32, device="cuda")
+    pb.apply_A(dev(x32), y)
+    torch.cuda.synchronize()
+    assert rel_l2(host(y), A @ x32.astype(np.float64)) <= 1e-5
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 3, 16), (2, 5, 8)])
+def test_apply_A_on_every_level(dim, k, N):
+    pb = _problem(dim, k, N)
+    for lev in range(pb.num_levels()):
+        Nl = 2 ** (lev + 1)
+        say("apply_A level", lev, Nl)
+        A, _, _ = oracle_ops(dim, k, Nl)
+        x, _ = vectors(dim, k, Nl)
+        y = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+        pb.apply_A(dev(x), y, level=lev)
+        torch.cuda.synchronize()
+        assert rel_l2(host(y), A @ x) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,k,N", SMALL)
+@pytest.mark.parametrize("x_is_zero", [False, True])
+def test_smoother_f64_matches_oracle(dim, k, N, x_is_zero):
+    say("smoother f64", dim, k, N, x_is_zero)
+    A, blocks, pidx = oracle_ops(dim, k, N)
+    x, b = vectors(dim, k, N)
+    om = 0.25
+    ref = O.avs_apply(A, blocks, pidx, x, b, om, 1, x_is_zero=x_is_zero)
+    pb = _problem(dim, k, N, omega=om)
+    xd = dev(x)
+    pb.apply_smoother(dev(b), xd, x_is_zero=x_is_zero)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xd), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 32), (2, 3, 32), (2, 4, 16), (2, 7, 8)])
+def test_smoother_f32_matches_oracle(dim, k, N):
+    say("smoother f32", dim, k, N)
+    A, blocks, pidx = oracle_ops(dim, k, N)
+    x, b = vectors(dim, k, N)
+    x32, b32 = x.astype(np.float32), b.astype(np.float32)
+    ref = O.avs_apply(A, blocks, pidx, x32.astype(np.float64), b32.astype(np.float64), 0.25, 1)
+    pb = _problem(dim, k, N, omega=0.25)
+    xd = dev(x32)
+    pb.apply_smoother(dev(b32), xd)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xd), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 5, 8), (2, 7, 4)])
+def test_vcycle_f64_matches_oracle(dim, k, N):
+    say("vcycle f64", dim, k, N)
+    H = O.Hierarchy(dim, k, N, omega=0.25)
+    _, b = vectors(dim, k, N)
+    ref = H.vcycle(b)
+    pb = _problem(dim, k, N, omega=0.25, vcycle_dtype=P.C0IP_F64)
+    xd = torch.empty(b.size, dtype=torch.float64, device="cuda")
+    pb.vcycle(dev(b), xd)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xd), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16)])
+def test_vcycle_f32_matches_oracle(dim, k, N):
+    say("vcycle f32", dim, k, N)
+    H = O.Hierarchy(dim, k, N, omega=0.25)
+    _, b = vectors(dim, k, N)
+    b32 = b.astype(np.float32)
+    ref = H.vcycle(b32.astype(np.float64))
+    pb = _problem(dim, k, N, omega=0.25)
+    xd = torch.empty(b.size, dtype=torch.float32, device="cuda")
+    pb.vcycle(dev(b32), xd)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xd), ref) <= 1e-4
+
+
+@pytest.mark.parametrize("k,N", [(2, 16), (3, 16)])
+def test_solve_f64_matches_oracle_iterations(k, N):
+    dim = 2
+    say("solve f64", dim, k, N)
+    A = O.assemble(dim, k, N)
+    _, b = vectors(dim, k, N)
+    H = O.Hierarchy(dim, k, N, omega=0.25)
+    xr, info_r = O.fgmres(A, b, H.vcycle, rtol=1e-8, restart=50)
+    pb = _problem(dim, k, N, omega=0.25, vcycle_dtype=P.C0IP_F64)
+    xd = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    info = pb.solve(dev(b), xd, rtol=1e-8)
+    assert info["converged"] == 1
+    assert info["iterations"] == info_r["iterations"]
+    assert info["rel_res_true"] <= 1.05e-8
+    res = np.linalg.norm(b - A @ host(xd)) / np.linalg.norm(b)
+    assert res <= 1.05e-8
+    assert rel_l2(host(xd), xr) <= 1e-6
+
+
+@pytest.mark.parametrize("k,N", [(2, 16), (3, 32), (5, 8)])
+def test_solve_mixed_precision(k, N):
+    dim = 2
+    say("solve mixed", dim, k, N)
+    A = O.assemble(dim, k, N)
+    _, b = vectors(dim, k, N)
+    p64 = _problem(dim, k, N, omega=0.25, vcycle_dtype=P.C0IP_F64)
+    p32 = _problem(dim, k, N, omega=0.25, vcycle_dtype=P.C0IP_F32)
+    x64 = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    x32 = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    i64 = p64.solve(dev(b), x64)
+    i32 = p32.solve(dev(b), x32)
+    assert i32["converged"] == 1 and i64["converged"] == 1
+    assert i32["iterations"] <= i64["iterations"] + 2
+    for xx in (x64, x32):
+        assert np.linalg.norm(b - A @ host(xx)) / np.linalg.norm(b) <= 1.05e-8
+    free = ~O.boundary_mask(dim, k, N)
+    import scipy.sparse.linalg as spla
+    xs = np.zeros(b.size)
+    xs[free] = spla.spsolve(A[free][:, free].tocsc(), b[free])
+    kappa_bound = 1e-8 * 1e6  # error <= cond(A) * residual; cond of these systems < 1e6
+    assert rel_l2(host(x32), xs) <= kappa_bound
+
+
+def _sample_nodes(dim, k, N, count, seed):
+    n1 = k * N + 1
+    rng = np.random.default_rng(seed)
+    picks = [(1, 1), (n1 - 2, n1 - 2), (1, n1 // 2), (k, k), (2 * k, 2 * k + 1), (n1 // 2, n1 // 2),
+             (n1 - 1 - k, 3), (0, 5)]
+    nodes = [i + n1 * j for i, j in picks]
+    nodes += list(rng.integers(0, n1 * n1, count))
+    return np.array(nodes)
+
+
+FULL = [(3, 512), (2, 512), (4, 512), (7, 256)]
+
+
+@pytest.mark.parametrize("k,N", FULL)
+def test_full_size_sampled_parity(k, N):
+    """Full-size 2D workloads in the bench's launch configuration: A x and
+    S(x, b) at sampled DoFs against the windowed oracle."""
+    dim = 2
+    say("full size sampled", dim, k, N)
+    x, b = vectors(dim, k, N)
+    nodes = _sample_nodes(dim, k, N, 24, 11)
+    pb = _problem(dim, k, N, omega=0.25)
+    y = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    pb.apply_A(dev(x), y)
+    xs = dev(x)
+    pb.apply_smoother(dev(b), xs)
+    torch.cuda.synchronize()
+    yh, sh = host(y), host(xs)
+    ya = O.apply_rows_windowed(dim, k, N, x, nodes)
+    scale = np.abs(ya).max()
+    assert np.abs(yh[nodes] - ya).max() <= 1e-12 * scale
+    sa = O.avs_nodes_windowed(dim, k, N, x, b, 0.25, nodes)
+    assert np.abs(sh[nodes] - sa).max() <= 1e-12 * np.abs(sa).max()
+    # boundary rows are exactly zero; no non-finite values anywhere
+    assert np.isfinite(yh).all() and np.isfinite(sh).all()
+    bd = O.boundary_mask(dim, k, N) if N <= 256 else None
+    if bd is not None:
+        assert np.all(yh[bd] == 0) and np.all(sh[bd] == 0)
+
+
+def test_abi_rejects_bad_arguments():
+    say("abi errors")
+    for kw in [dict(dim=4, N=8, k=3), dict(dim=2, N=6, k=3), dict(dim=2, N=8, k=1), dict(dim=2, N=8, k=8)]:
+        with pytest.raises(P.C0ipError) as e:
+            P.Problem(kw["dim"], kw["N"], kw["k"])
+        assert e.value.status == -1
+    with pytest.raises(P.C0ipError) as e:
+        P.Problem(2, 8, 3, omega=-1.0)
+    assert e.value.status == -1
+    with pytest.raises(P.C0ipError) as e:
+        P.Problem(2, 8, 3, scatter_mode=1)
+    assert e.value.status == -6
+    pb = P.Problem(2, 8, 3)
+    with pytest.raises(ValueError):
+        pb.apply_A(torch.zeros(10, dtype=torch.float64, device="cuda"),
+                   torch.zeros(10, dtype=torch.float64, device="cuda"))
+    lib = P.load_library()
+    assert lib.c0ip_apply_A(pb._h, 0, 0, None, None) == -1
+    assert lib.c0ip_apply_A(pb._h, 99, 0, 1, 2) == -1
+
+
+def test_solve_not_converged_and_nan():
+    dim, k, N = 2, 2, 16
+    say("solve status", dim, k, N)
+    _, b = vectors(dim, k, N)
+    pb = _problem(dim, k, N)
+    x = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    info = pb.solve(dev(b), x, max_iters=3, raise_on_nonconv=False)
+    assert info["iterations"] == 3 and info["converged"] == 0
+    bn = b.copy()
+    bn[100] = np.nan
+    with pytest.raises(P.C0ipError) as e:
+        pb.solve(dev(bn), x)
+    assert e.value.status == -5

@@ -1,0 +1,75 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol of
+include/c0ip.h, and its host-side set-up (1D factors of Sec. 4 and the
+fast-diagonalisation patch inverse of eq. inverse) matches the exact
+1D factors and the oracle's dense LU of the patch matrices."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2412_05082_amd as P
+from tests import sym1d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    txt = open(os.path.join(ROOT, "include", "c0ip.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(c0ip_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    syms = _header_symbols()
+    assert "c0ip_create" in syms and "c0ip_solve" in syms
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+@pytest.mark.parametrize("k,N", [(2, 2), (2, 8), (3, 4), (4, 2)])
+def test_host_1d_factors_match_exact(k, N):
+    M, L, B = P.host_matrices_1d(k, N)
+    Ms, Ls, Bs = sym1d.matrices_1d(k, N)
+    bd = np.zeros(k * N + 1, bool)
+    bd[[0, -1]] = True
+    for X, Y in [(M, Ms), (L, Ls), (B, Bs)]:
+        Y = Y.copy()
+        Y[bd, :] = 0
+        Y[:, bd] = 0
+        assert np.abs(X - Y).max() <= 1e-13 * np.abs(Y).max()
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 2), (2, 2, 8), (2, 3, 8), (2, 5, 4), (2, 7, 4), (3, 2, 4), (3, 3, 2)])
+def test_host_fdm_inverse_matches_dense_lu(dim, k, N):
+    """eq. inverse is an identity: the library's Q D^-1 Q^T equals the
+    inverse of the oracle's separable patch matrix (explicit quadrature),
+    for every boundary variant of the patch."""
+    At = O.assemble(dim, k, N, bulk="diag")
+    verts = O.patch_vertices(dim, N)
+    pick = {}
+    for v in verts:
+        key = tuple((1 if vm == 1 else 0) | (2 if vm == N - 1 else 0) for vm in v)
+        pick.setdefault(key, v)
+    for key, v in pick.items():
+        pidx = O.patch_indices(dim, k, N, v[None, :])
+        Av = O.patch_blocks(At, pidx)[0]
+        Ainv = P.host_patch_inverse(dim, k, N, [int(t) for t in v])
+        ref = np.linalg.inv(Av)
+        kappa = np.linalg.cond(Av)
+        assert np.abs(Ainv - ref).max() <= 50 * kappa * 1e-16 * np.abs(ref).max(), (key, kappa)
+        r = np.random.default_rng(0).uniform(-1, 1, Av.shape[0])
+        u = Ainv @ r
+        assert np.linalg.norm(Av @ u - r) <= 1e-12 * np.linalg.norm(r) * max(1.0, kappa / 1e3)
+
+
+def test_host_entry_points_reject_bad_arguments():
+    with pytest.raises(P.C0ipError) as e:
+        P.host_matrices_1d(1, 4)
+    assert e.value.status == -1
+    with pytest.raises(P.C0ipError):
+        P.host_patch_inverse(2, 3, 4, [0, 1])
+    with pytest.raises(P.C0ipError):
+        P.host_patch_inverse(2, 3, 6, [1, 1])  # not a power of two

@@ -123,3 +123,22 @@ def test_windowed_rows_equal_global_rows():
     # and a row just outside the exact set differs (the window really is cut)
     bad = np.where(~win.exact_rows() & win.free)[0]
     assert np.abs(yw[bad] - yg[win.gidx[bad]]).max() > 1e-6 * np.abs(yg).max()
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 3, 16), (3, 2, 8)])
+def test_windowed_sampled_outputs_equal_global(dim, k, N):
+    """The sampled full-size oracle (windows of cells around each output)
+    reproduces the global A x and S(x,b) exactly."""
+    from paper_2412_05082_amd.inputs import seeded_vector
+    A = O.assemble(dim, k, N)
+    At = O.assemble(dim, k, N, bulk="diag")
+    pidx = O.patch_indices(dim, k, N)
+    x = seeded_vector(dim, k, N, 1)
+    b = seeded_vector(dim, k, N, 0)
+    rng = np.random.default_rng(5)
+    nodes = rng.choice(A.shape[0], 12, replace=False)
+    y = A @ x
+    assert np.abs(O.apply_rows_windowed(dim, k, N, x, nodes) - y[nodes]).max() <= 1e-13 * np.abs(y).max()
+    S = O.avs_apply(A, O.patch_blocks(At, pidx), pidx, x, b, 0.25)
+    Sw = O.avs_nodes_windowed(dim, k, N, x, b, 0.25, nodes)
+    assert np.abs(Sw - S[nodes]).max() <= 1e-13 * np.abs(S).max()
