@@ -1,8 +1,12 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances: float64 results within 1e-12 relative l2 of the oracle;
-float32 smoother/operator applies within 1e-5 relative l2 of the float64
-oracle.  Sizes span several tiles and ragged last tiles; the full-size
+Tolerances: float64 results within 1e-12 relative l2 of the oracle, or
+2 kappa(A~_v) eps where the patch matrices are worse conditioned (k >= 6:
+two correct float64 local solves differ by up to ~kappa eps);
+float32 operator applies within 1e-5 and float32 smoother applies within
+max(1e-5, 0.05 kappa eps32) relative l2 of the float64 oracle (1e-5 for
+k <= 4; above, the float32 residual's rounding, amplified by the local
+solve's conditioning, sets the limit).  Sizes span several tiles and ragged last tiles; the full-size
 workloads (2D Q3 512^2 and the degree sweep) are checked on sampled
 outputs computed by the windowed oracle.
 """
@@ -12,7 +16,7 @@ import torch
 
 import oracle as O
 import paper_2412_05082_amd as P
-from tests.gpu_util import dev, host, oracle_ops, rel_l2, say, vectors
+from tests.gpu_util import dev, fp32_tol, fp64_tol, host, oracle_ops, rel_l2, say, vectors
 
 pytestmark = pytest.mark.gpu
 
@@ -77,10 +81,10 @@ def test_smoother_f64_matches_oracle(dim, k, N, x_is_zero):
     xd = dev(x)
     pb.apply_smoother(dev(b), xd, x_is_zero=x_is_zero)
     torch.cuda.synchronize()
-    assert rel_l2(host(xd), ref) <= 1e-12
+    assert rel_l2(host(xd), ref) <= fp64_tol(dim, k, N)
 
 
-@pytest.mark.parametrize("dim,k,N", [(2, 2, 32), (2, 3, 32), (2, 4, 16), (2, 7, 8)])
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 32), (2, 3, 32), (2, 4, 16), (2, 5, 8), (2, 6, 8), (2, 7, 8)])
 def test_smoother_f32_matches_oracle(dim, k, N):
     say("smoother f32", dim, k, N)
     A, blocks, pidx = oracle_ops(dim, k, N)
@@ -91,7 +95,12 @@ def test_smoother_f32_matches_oracle(dim, k, N):
     xd = dev(x32)
     pb.apply_smoother(dev(b32), xd)
     torch.cuda.synchronize()
-    assert rel_l2(host(xd), ref) <= 1e-5
+    assert rel_l2(host(xd), ref) <= fp32_tol(dim, k, N)
+    x0 = torch.zeros(x.size, dtype=torch.float32, device="cuda")
+    pb.apply_smoother(dev(b32), x0, x_is_zero=True)
+    ref0 = O.avs_apply(A, blocks, pidx, None, b32.astype(np.float64), 0.25, 1, x_is_zero=True)
+    torch.cuda.synchronize()
+    assert rel_l2(host(x0), ref0) <= 1e-5
 
 
 @pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 5, 8), (2, 7, 4)])
@@ -104,7 +113,7 @@ def test_vcycle_f64_matches_oracle(dim, k, N):
     xd = torch.empty(b.size, dtype=torch.float64, device="cuda")
     pb.vcycle(dev(b), xd)
     torch.cuda.synchronize()
-    assert rel_l2(host(xd), ref) <= 1e-11
+    assert rel_l2(host(xd), ref) <= 10 * fp64_tol(dim, k, N)
 
 
 @pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16)])
@@ -196,7 +205,7 @@ def test_full_size_sampled_parity(k, N):
     scale = np.abs(ya).max()
     assert np.abs(yh[nodes] - ya).max() <= 1e-12 * scale
     sa = O.avs_nodes_windowed(dim, k, N, x, b, 0.25, nodes)
-    assert np.abs(sh[nodes] - sa).max() <= 1e-12 * np.abs(sa).max()
+    assert np.abs(sh[nodes] - sa).max() <= fp64_tol(dim, k, N) * np.abs(sa).max()
     # boundary rows are exactly zero; no non-finite values anywhere
     assert np.isfinite(yh).all() and np.isfinite(sh).all()
     bd = O.boundary_mask(dim, k, N) if N <= 256 else None
