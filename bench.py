@@ -40,7 +40,34 @@ def parse():
     ap.add_argument("--reps", type=int, default=30, help="kernel timing repetitions")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-N", type=int, default=64, help="cells per direction of the oracle sample")
+    ap.add_argument("--only", default=None,
+                    choices=["matvec_f64", "smoother_f64", "matvec_f32", "smoother_f32", "copy_f64"],
+                    help="run only this kernel's timing loop (for counter collection) and print its ms")
     return ap.parse_args()
+
+
+def only_kernel(args):
+    """One kernel's timing loop on the bench workload, nothing else: used to
+    collect hardware counters for it (and, with copy_f64, for a plain device
+    copy of one float64 vector, the reference for scaling those counters)."""
+    import torch
+
+    import paper_2412_05082_amd as P
+    from paper_2412_05082_amd.inputs import seeded_vector
+    dim, k, N = 2, args.k, args.N
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(seeded_vector(dim, k, N, 1)).to(dev)
+    b = torch.from_numpy(seeded_vector(dim, k, N, 0)).to(dev)
+    n = x.numel()
+    if args.only.endswith("f32"):
+        x, b = x.float(), b.float()
+    y = torch.zeros_like(x)
+    pb = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F32)
+    fn = {"matvec_f64": lambda: pb.apply_A(x, y), "matvec_f32": lambda: pb.apply_A(x, y),
+          "smoother_f64": lambda: pb.apply_smoother(b, y), "smoother_f32": lambda: pb.apply_smoother(b, y),
+          "copy_f64": lambda: y.copy_(x)}[args.only]
+    ms = time_kernel(lambda _: fn(), [None], args.reps, torch)
+    print(json.dumps({"only": args.only, "ms": ms, "dofs": n, "reps": args.reps}), flush=True)
 
 
 def time_kernel(fn, sets, reps, torch):
@@ -88,6 +115,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.only:
+        only_kernel(args)
+        return
     import numpy as np
     import torch
 
