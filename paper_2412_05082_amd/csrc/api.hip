@@ -92,11 +92,13 @@ struct c0ip_problem {
   std::vector<double> ptab;  // prolongation table (float64 host copy)
   DevBuf<double> A0inv;
   // Krylov work space
-  DevBuf<double> V, w, partial, hdev, ydev, r64;
+  DevBuf<double> V, w, u, partial, hdev, coef, ydev, r64;
   DevBuf<double> Z64;
   DevBuf<float> Z32;
-  DevBuf<int> nanflag;
-  int kry_m = 0;
+  double* hpin = nullptr;  // pinned host staging for the per-step reductions
+  ~c0ip_problem() {
+    if (hpin) (void)hipHostFree(hpin);
+  }
 
   int64_t ntot(int l) const { return lv[l]->ntot; }
   template <typename T>
@@ -394,6 +396,32 @@ c0ip_status c0ip_vcycle(c0ip_problem* p, c0ip_dtype dtype, const void* b, void* 
   return C0IP_OK;
 }
 
+// Givens QR of the (j+2) x (j+1) Hessenberg H (row-major, leading dim m)
+// applied to g0 e_1; returns |g_{j+1}| and leaves R, g for back substitution.
+static double hessenberg_lsq(const std::vector<double>& H, int m, int j, double g0, std::vector<double>& R,
+                             std::vector<double>& g) {
+  const int nr = j + 2, nc = j + 1;
+  R.assign((size_t)nr * nc, 0.0);
+  for (int r = 0; r < nr; ++r)
+    for (int c = 0; c < nc; ++c) R[(size_t)r * nc + c] = H[(size_t)r * m + c];
+  g.assign(nr, 0.0);
+  g[0] = g0;
+  for (int c = 0; c < nc; ++c) {
+    const double a = R[(size_t)c * nc + c], b = R[(size_t)(c + 1) * nc + c];
+    const double den = std::hypot(a, b);
+    const double cs = den > 0 ? a / den : 1.0, sn = den > 0 ? b / den : 0.0;
+    for (int cc = c; cc < nc; ++cc) {
+      const double x = R[(size_t)c * nc + cc], y = R[(size_t)(c + 1) * nc + cc];
+      R[(size_t)c * nc + cc] = cs * x + sn * y;
+      R[(size_t)(c + 1) * nc + cc] = -sn * x + cs * y;
+    }
+    const double x = g[c], y = g[c + 1];
+    g[c] = cs * x + sn * y;
+    g[c + 1] = -sn * x + cs * y;
+  }
+  return std::fabs(g[nr - 1]);
+}
+
 c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const double* b, double* x,
                        c0ip_solve_info* info) {
   g_err.clear();
@@ -407,126 +435,133 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   hipStream_t s = p->stream;
   c0ip_solve_info inf{};
   auto t0 = std::chrono::steady_clock::now();
-  double t_vc = 0, t_ar = 0;
+  double t_vc = 0;
   c0ip_status result = C0IP_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr, ef = nullptr;
   try {
     const int nblk = c0ip::multidot_blocks(n);
-    p->V.alloc((size_t)(m + 1) * n);
+    p->V.alloc((size_t)m * n);
     p->w.alloc(n);
     p->r64.alloc(n);
+    p->u.alloc(n);
     p->partial.alloc((size_t)(2 * m + 3) * nblk);
     p->hdev.alloc(2 * m + 3);
+    p->coef.alloc(2 * m + 5);
     p->ydev.alloc(m);
-    p->nanflag.alloc(1);
+    if (!p->hpin) p->check(hipHostMalloc((void**)&p->hpin, sizeof(double) * (4 * 64 + 16)), "pinned alloc");
     if (f32) {
       p->Z32.alloc((size_t)m * n);
       for (int l = 0; l <= Lf; ++l) p->prepare<float>(l);
     } else {
       p->Z64.alloc((size_t)m * n);
     }
-    hipEvent_t e0, e1;
     p->check(hipEventCreate(&e0), "event");
     p->check(hipEventCreate(&e1), "event");
-    std::vector<double> hh(2 * m + 3);
-    auto dots = [&](int cnt, const double* Vp, const double* wp, int off) {
-      p->check(c0ip::launch_multidot(n, cnt, Vp, n, wp, p->partial.p, nblk, s), "multidot");
-      p->check(c0ip::launch_reduce_partials(cnt, nblk, p->partial.p, p->hdev.p + off, 0, s), "reduce");
-    };
-    auto fetch = [&](int cnt) {
-      p->check(hipMemcpyAsync(hh.data(), p->hdev.p, cnt * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+    p->check(hipEventCreateWithFlags(&ef, hipEventDisableTiming), "event");
+    double* hh = p->hpin;  // [0, 2m+3): dots; [2m+3, 4m+8): coefficients
+    auto norm2 = [&](const double* v) {
+      p->check(c0ip::launch_multidot(n, 1, v, n, v, p->partial.p, nblk, s), "multidot");
+      p->check(c0ip::launch_reduce_partials(1, nblk, p->partial.p, p->hdev.p, 0, s), "reduce");
+      p->check(hipMemcpyAsync(hh, p->hdev.p, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
       p->check(hipStreamSynchronize(s), "sync");
+      return hh[0];
     };
     const auto& cf64 = p->work<double>(Lf).coef;
     // ||b|| over the free DoFs (boundary entries of b are ignored): r = b - A 0
     p->check(c0ip::launch_fill(n, 0.0, p->w.p, s), "fill");
     p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, p->w.p, b, p->r64.p, s), "mask b");
-    dots(1, p->r64.p, p->r64.p, 0);
-    fetch(1);
-    const double bnorm = std::sqrt(hh[0]);
+    const double bnorm = std::sqrt(norm2(p->r64.p));
     if (!std::isfinite(bnorm)) throw c0ip_status(C0IP_ENAN);
-    // r = b - A x0
     if (opts->x0_is_zero) {
       p->check(c0ip::launch_fill(n, 0.0, x, s), "fill");
     } else {
       p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, x, b, p->r64.p, s), "residual");
     }
-    dots(1, p->r64.p, p->r64.p, 0);
-    fetch(1);
-    double beta = std::sqrt(hh[0]);
-    std::vector<double> hist;
-    hist.push_back(beta);
+    double beta = std::sqrt(norm2(p->r64.p));
+    std::vector<double> hist{beta};
     int its = 0;
     bool converged = bnorm == 0.0 || beta <= opts->rtol * bnorm;
-    if (bnorm == 0.0) p->check(c0ip::launch_fill(n, 0.0, x, s), "fill");
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), R, g, y(m);
     while (!converged && its < opts->max_iters) {
       if (!(beta > 0) || !std::isfinite(beta)) throw c0ip_status(C0IP_ENAN);
-      // V_0 = r / beta
-      dots(1, p->r64.p, p->r64.p, 0);
-      p->check(c0ip::launch_normalize(n, p->r64.p, p->hdev.p, p->V.p, s), "normalize");
+      // lagged vector u = r / beta (re-normalised exactly at step 0)
+      p->check(c0ip::launch_multidot(n, 1, p->r64.p, n, p->r64.p, p->partial.p, nblk, s), "multidot");
+      p->check(c0ip::launch_reduce_partials(1, nblk, p->partial.p, p->hdev.p, 0, s), "reduce");
+      p->check(c0ip::launch_normalize(n, p->r64.p, p->hdev.p, p->u.p, s), "normalize");
       std::fill(H.begin(), H.end(), 0.0);
-      std::fill(g.begin(), g.end(), 0.0);
-      g[0] = beta;
+      double g0 = beta;
       int jdone = 0;
       bool stop = false;
       for (int j = 0; j < m && !stop; ++j) {
-        double* Vj = p->V.p + (size_t)j * n;
         p->check(hipEventRecord(e0, s), "event");
+        const double* Zp;
+        bool zf32 = f32;
         if (f32) {
           float* Zj = p->Z32.p + (size_t)j * n;
           LevelWork<float>& wf = p->work<float>(Lf);
-          p->check(c0ip::launch_cast<double, float>(n, Vj, wf.b.p, s), "cast");
+          p->check(c0ip::launch_cast<double, float>(n, p->u.p, wf.b.p, s), "cast");
           p->mg_level<float>(Lf, wf.b.p, Zj);
           p->check(hipEventRecord(e1, s), "event");
           p->check(c0ip::launch_apply<float, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
+          Zp = nullptr;
         } else {
           double* Zj = p->Z64.p + (size_t)j * n;
-          p->mg_level<double>(Lf, Vj, Zj);
+          p->mg_level<double>(Lf, p->u.p, Zj);
           p->check(hipEventRecord(e1, s), "event");
           p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
+          Zp = Zj;
         }
-        // classical Gram-Schmidt, twice
-        dots(j + 1, p->V.p, p->w.p, 0);
-        p->check(c0ip::launch_multiaxpy(n, j + 1, p->V.p, n, p->hdev.p, p->w.p, s), "axpy");
-        dots(j + 1, p->V.p, p->w.p, j + 1);
-        p->check(c0ip::launch_multiaxpy(n, j + 1, p->V.p, n, p->hdev.p + j + 1, p->w.p, s), "axpy");
-        dots(1, p->w.p, p->w.p, 2 * j + 2);
-        fetch(2 * j + 3);
+        (void)Zp;
+        (void)zf32;
+        // one reduction: V^T u, V^T w, u.u, u.w, w.w; coefficients on the device
+        p->check(c0ip::launch_arnoldi_dots(n, j, p->V.p, n, p->u.p, p->w.p, p->partial.p, nblk, s), "dots");
+        p->check(c0ip::launch_reduce_partials(2 * j + 3, nblk, p->partial.p, p->hdev.p, 0, s), "reduce");
+        p->check(c0ip::launch_arnoldi_coef(j, p->hdev.p, p->coef.p, s), "coef");
+        p->check(hipMemcpyAsync(hh, p->hdev.p, (2 * j + 3) * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+        p->check(hipMemcpyAsync(hh + 2 * m + 3, p->coef.p, (2 * j + 5) * sizeof(double), hipMemcpyDeviceToHost, s),
+                 "D2H");
+        p->check(hipEventRecord(ef, s), "event");
+        // V_j = (u - V s)/alpha ; u <- w - V c - V_j h_v   (overlaps the host work below)
+        p->check(c0ip::launch_arnoldi_update(n, j, p->V.p, n, p->u.p, p->w.p, p->coef.p, p->V.p + (size_t)j * n, s),
+                 "update");
+        p->check(hipEventSynchronize(ef), "sync");
         float ms = 0;
         p->check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
         t_vc += ms * 1e-3;
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[j + 1 + i];
-        const double hn = std::sqrt(std::max(hh[2 * j + 2], 0.0));
-        if (!std::isfinite(hn)) throw c0ip_status(C0IP_ENAN);
-        H[(size_t)(j + 1) * m + j] = hn;
-        for (int i = 0; i < j; ++i) {
-          double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
-          H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
-          H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+        const double* d = hh;
+        const double* cf = hh + 2 * m + 3;
+        const double alpha = cf[2 * j + 2], hv = cf[2 * j + 3];
+        if (!std::isfinite(alpha) || !std::isfinite(hv) || !std::isfinite(d[2 * j + 2]))
+          throw c0ip_status(C0IP_ENAN);
+        if (j == 0) {
+          g0 = beta * alpha;  // r = beta u = beta alpha V_0
+        } else {
+          for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += d[i];
+          H[(size_t)j * m + (j - 1)] = alpha;
         }
-        double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
-        double den = std::hypot(a, bb);
-        cs[j] = a / den;
-        sn[j] = bb / den;
-        H[(size_t)j * m + j] = den;
-        H[(size_t)(j + 1) * m + j] = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
+        double cc = 0;
+        for (int i = 0; i < j; ++i) {
+          H[(size_t)i * m + j] = d[j + i];
+          cc += d[j + i] * d[j + i];
+        }
+        H[(size_t)j * m + j] = hv;
+        const double ww = d[2 * j + 2];
+        double est2 = ww - cc - hv * hv;
+        if (!(est2 > 1e-10 * ww)) est2 = norm2(p->u.p);  // heavy cancellation: exact norm
+        H[(size_t)(j + 1) * m + j] = std::sqrt(std::max(est2, 0.0));
+        const double res = hessenberg_lsq(H, m, j, g0, R, g);
         ++its;
         jdone = j + 1;
-        hist.push_back(std::fabs(g[j + 1]));
-        if (std::fabs(g[j + 1]) <= opts->rtol * bnorm || hn == 0.0 || its >= opts->max_iters) {
-          stop = true;
-        } else {
-          p->check(c0ip::launch_normalize(n, p->w.p, p->hdev.p + 2 * j + 2, p->V.p + (size_t)(j + 1) * n, s),
-                   "normalize");
-        }
+        hist.push_back(res);
+        if (res <= opts->rtol * bnorm || H[(size_t)(j + 1) * m + j] == 0.0 || its >= opts->max_iters) stop = true;
       }
-      // y = H^{-1} g, x += Z y
+      // y = R^{-1} g, x += Z y
+      hessenberg_lsq(H, m, jdone - 1, g0, R, g);
+      const int nc = jdone;
       for (int i = jdone - 1; i >= 0; --i) {
         double t = g[i];
-        for (int l2 = i + 1; l2 < jdone; ++l2) t -= H[(size_t)i * m + l2] * y[l2];
-        y[i] = t / H[(size_t)i * m + i];
+        for (int l2 = i + 1; l2 < jdone; ++l2) t -= R[(size_t)i * nc + l2] * y[l2];
+        y[i] = t / R[(size_t)i * nc + i];
       }
       p->check(hipMemcpyAsync(p->ydev.p, y.data(), jdone * sizeof(double), hipMemcpyHostToDevice, s), "H2D");
       if (f32)
@@ -534,14 +569,10 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
       else
         p->check(c0ip::launch_update_solution<double>(n, jdone, p->Z64.p, n, p->ydev.p, x, s), "update");
       p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, x, b, p->r64.p, s), "residual");
-      dots(1, p->r64.p, p->r64.p, 0);
-      fetch(1);
-      beta = std::sqrt(hh[0]);
+      beta = std::sqrt(norm2(p->r64.p));
       converged = hist.back() <= opts->rtol * bnorm;
     }
     p->check(hipStreamSynchronize(s), "sync");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     inf.iterations = its;
     inf.converged = converged ? 1 : 0;
     inf.rel_res_est = bnorm > 0 ? hist.back() / bnorm : 0.0;
@@ -555,11 +586,13 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     (void)hipStreamSynchronize(s);
     result = fail(st, "non-finite value in the Krylov iteration");
   }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ef) (void)hipEventDestroy(ef);
   auto t1 = std::chrono::steady_clock::now();
   inf.seconds_total = std::chrono::duration<double>(t1 - t0).count();
   inf.seconds_vcycle = t_vc;
   inf.seconds_arnoldi = std::max(0.0, inf.seconds_total - t_vc);
-  (void)t_ar;
   if (info) *info = inf;
   return result;
 }

@@ -71,12 +71,25 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_
 
 int multidot_blocks(int64_t n);
 
+// Arnoldi step with delayed re-orthogonalisation (see kernels_common.hip).
+// dots: partial[(2j+3) * nblk]; coef: one thread, writes 2j+5 values;
+// update: V_j = (u - V s)/alpha into vout, u <- w - V f - (h_v/alpha) u.
+hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, const double* u, const double* w,
+                               double* partial, int nblk, hipStream_t s);
+hipError_t launch_arnoldi_coef(int j, const double* d, double* coef, hipStream_t s);
+hipError_t launch_arnoldi_update(int64_t n, int j, const double* V, int64_t ldv, double* u, const double* w,
+                                 const double* coef, double* vout, hipStream_t s);
+
 // Per-dimension operator and smoother launchers (k dispatched at run time).
 template <typename Tin, typename T>
 hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s);
 template <typename T>
 hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
                           hipStream_t s);
+template <typename T>
+hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong2d(int k, int Nc, const T* table, const T* ec, T* xf, hipStream_t s);
 template <typename Tin, typename T>
 hipError_t launch_apply3d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s);
 template <typename T>

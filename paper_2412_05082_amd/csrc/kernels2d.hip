@@ -124,35 +124,56 @@ __device__ __forceinline__ void y_sweeps(const T* __restrict__ sU, const T* __re
   }
 }
 
+// Row-class tables have at most 5k+2 classes (2k+1 per boundary end plus k
+// periodic ones, or one per row on levels with kN+1 <= 5k+2 nodes).
+template <int K> __host__ __device__ constexpr int tab_max() { return 3 * (5 * K + 2) * (4 * K + 1); }
+
 template <typename Tin, typename T, int K, int TXC, int TYC, bool RES>
 __global__ __launch_bounds__(kThreads) void apply2d_kernel(const Tin* __restrict__ x, const T* __restrict__ b,
                                                            T* __restrict__ y, int n1, const T* __restrict__ tab,
                                                            int nclass, int left, int right0, int periodic) {
   constexpr int H = 2 * K, TX = TXC * K, TY = TYC * K, RX = TX + 2 * H, RY = TY + 2 * H;
+  constexpr int NL = (RY * RX + kThreads - 1) / kThreads;
   __shared__ T sX[RY * RX];
   __shared__ T sU[RY * TX];
   __shared__ T sV[(TY + 2 * K) * TX];
   __shared__ T sW[(TY + 2 * K) * TX];
+  __shared__ T sTab[tab_max<K>()];
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  for (int e = threadIdx.x; e < RY * RX; e += kThreads) {
-    const int r = e / RX, c = e - r * RX;
-    const int gy = y0 - H + r, gx = x0 - H + c;
-    T v = 0;
-    if (gy >= 0 && gy < n1 && gx >= 0 && gx < n1) v = (T)x[(size_t)gy * n1 + gx];
-    sX[e] = v;
+  const bool xin = periodic && x0 >= left && x0 + TX <= right0;
+  const bool yin = periodic && y0 >= left && y0 + TY <= right0;
+  {
+    // all global loads of the tile are issued before the first LDS store
+    T v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      const int r = e / RX, c = e - r * RX;
+      const int gy = y0 - H + r, gx = x0 - H + c;
+      v[q] = (e < RY * RX && gy >= 0 && gy < n1 && gx >= 0 && gx < n1) ? (T)x[(size_t)gy * n1 + gx] : T(0);
+    }
+    if (!(xin && yin)) {
+      const int ntab = 3 * nclass * (4 * K + 1);
+      for (int e = threadIdx.x; e < ntab; e += kThreads) sTab[e] = tab[e];
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < RY * RX) sX[e] = v[q];
+    }
   }
   __syncthreads();
-  const bool xin = periodic && x0 >= left && x0 + TX <= right0;
+  // interior tiles: wave-uniform coefficient addresses in the global table
+  // (scalar loads); boundary tiles: per-lane class rows from the LDS copy
   if (xin)
     x_sweeps<T, K, TXC, TYC, true>(sX, sU, sV, sW, x0, n1, tab, nclass, left, right0, periodic);
   else
-    x_sweeps<T, K, TXC, TYC, false>(sX, sU, sV, sW, x0, n1, tab, nclass, left, right0, periodic);
+    x_sweeps<T, K, TXC, TYC, false>(sX, sU, sV, sW, x0, n1, sTab, nclass, left, right0, periodic);
   __syncthreads();
-  const bool yin = periodic && y0 >= left && y0 + TY <= right0;
   if (yin)
     y_sweeps<T, K, TXC, TYC, true, RES>(sU, sV, sW, x0, y0, n1, tab, nclass, left, right0, periodic, b, y);
   else
-    y_sweeps<T, K, TXC, TYC, false, RES>(sU, sV, sW, x0, y0, n1, tab, nclass, left, right0, periodic, b, y);
+    y_sweeps<T, K, TXC, TYC, false, RES>(sU, sV, sW, x0, y0, n1, sTab, nclass, left, right0, periodic, b, y);
 }
 
 template <int K> struct ApplyTile2D;
@@ -184,22 +205,37 @@ __device__ __forceinline__ int variant(int v, int N) { return (v == 1 ? 1 : 0) |
 template <typename T, int K, int TC>
 __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__ r, const T* __restrict__ xin,
                                                            T* __restrict__ xout, int N, int n1,
-                                                           const T* __restrict__ Q, const T* __restrict__ lam,
+                                                           const T* __restrict__ Qg, const T* __restrict__ lamg,
                                                            T omega) {
   constexpr int n = 2 * K - 1, NN = n * n, NP = TC + 1, S = (TC + 2) * K - 1;
+  constexpr int NL = (S * S + kThreads - 1) / kThreads;
   __shared__ T sR[S * S];
   __shared__ T sA[NP * NP * NN];
   __shared__ T sB[NP * NP * NN];
+  __shared__ T sQ[4 * NN];
+  __shared__ T sLam[4 * n];
   const int cx0 = blockIdx.x * TC, cy0 = blockIdx.y * TC;
   const int ox = (cx0 - 1) * K + 1, oy = (cy0 - 1) * K + 1;  // global node of region (0,0)
-  for (int e = threadIdx.x; e < S * S; e += kThreads) {
-    const int rr = e / S, cc = e - rr * S;
-    const int gy = oy + rr, gx = ox + cc;
-    T v = 0;
-    if (gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2) v = r[(size_t)gy * n1 + gx];
-    sR[e] = v;
+  {
+    T v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      const int rr = e / S, cc = e - rr * S;
+      const int gy = oy + rr, gx = ox + cc;
+      v[q] = (e < S * S && gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2) ? r[(size_t)gy * n1 + gx] : T(0);
+    }
+    for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
+    for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < S * S) sR[e] = v[q];
+    }
   }
   __syncthreads();
+  const T* Q = sQ;
+  const T* lam = sLam;
   // forward along x: t[a][c] = sum_c' Qx[c'][c] r[a][c']
   for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
     const int p = it / n, a = it - p * n;
@@ -314,6 +350,142 @@ hipError_t patch2d_k(int N, const LevelEig<T>& e, const T* r, const T* xin, T* x
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ transfers
+// Restriction b_c = P^T r_f and prolongation x_f += P e_c in one launch each:
+// a workgroup owns TCC x TCC coarse cells, stages its fine (or coarse)
+// window in LDS and applies the 1D embedding table along x, then along y.
+// Table T[s][p][a]: value of coarse-cell basis a at the fine node of
+// position p in fine cell 2cc+s.
+
+template <int K> struct TransferTile2D { static constexpr int TCC = K <= 4 ? 8 : 4; };
+
+template <typename T, int K, int TCC>
+__global__ __launch_bounds__(kThreads) void restrict2d_kernel(const T* __restrict__ rf, T* __restrict__ bc, int Nc,
+                                                              const T* __restrict__ tab) {
+  constexpr int CT = TCC * K, F = 2 * K * (TCC + 1), NT = 2 * K * (K + 1);
+  constexpr int NL = (F * F + kThreads - 1) / kThreads;
+  __shared__ T sF[F * F];
+  __shared__ T sT[F * CT];
+  __shared__ T sTb[NT];
+  const int nf = 2 * K * Nc + 1, nc = K * Nc + 1;
+  const int c0x = blockIdx.x * TCC, c0y = blockIdx.y * TCC;
+  const int fx0 = 2 * K * (c0x - 1), fy0 = 2 * K * (c0y - 1);
+  {
+    T v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      const int rr = e / F, cc = e - rr * F;
+      const int gy = fy0 + rr, gx = fx0 + cc;
+      v[q] = (e < F * F && gy >= 0 && gy < nf && gx >= 0 && gx < nf) ? rf[(size_t)gy * nf + gx] : T(0);
+    }
+    for (int e = threadIdx.x; e < NT; e += kThreads) sTb[e] = tab[e];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < F * F) sF[e] = v[q];
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < F * CT; it += kThreads) {
+    const int rr = it / CT, l = it - rr * CT;
+    const int I = c0x * K + l, cl = l / K, a = l - cl * K;  // coarse cell c0x+cl, position a
+    const T* row = sF + rr * F + 2 * K * (cl + 1);
+    T v = 0;
+#pragma unroll
+    for (int q = 0; q < 2 * K; ++q) v += sTb[q * (K + 1) + a] * row[q];
+    if (a == 0) {
+#pragma unroll
+      for (int q = 0; q < 2 * K; ++q) v += sTb[q * (K + 1) + K] * row[q - 2 * K];
+    }
+    sT[it] = (I > 0 && I < nc - 1) ? v : T(0);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < CT * CT; it += kThreads) {
+    const int m = it / CT, l = it - m * CT;
+    const int I = c0x * K + l, J = c0y * K + m;
+    if (I >= nc || J >= nc) continue;
+    const int cm = m / K, a = m - cm * K;
+    const T* col = sT + (2 * K * (cm + 1)) * CT + l;
+    T v = 0;
+#pragma unroll
+    for (int q = 0; q < 2 * K; ++q) v += sTb[q * (K + 1) + a] * col[q * CT];
+    if (a == 0) {
+#pragma unroll
+      for (int q = 0; q < 2 * K; ++q) v += sTb[q * (K + 1) + K] * col[(q - 2 * K) * CT];
+    }
+    bc[(size_t)J * nc + I] = (J > 0 && J < nc - 1) ? v : T(0);
+  }
+}
+
+template <typename T, int K, int TCC>
+__global__ __launch_bounds__(kThreads) void prolong2d_kernel(const T* __restrict__ ec, T* __restrict__ xf, int Nc,
+                                                             const T* __restrict__ tab) {
+  constexpr int CW = TCC * K + 1, FT = 2 * K * TCC, NT = 2 * K * (K + 1);
+  constexpr int NL = (CW * CW + kThreads - 1) / kThreads;
+  __shared__ T sC[CW * CW];
+  __shared__ T sT[CW * FT];
+  __shared__ T sTb[NT];
+  const int nf = 2 * K * Nc + 1, nc = K * Nc + 1;
+  const int c0x = blockIdx.x * TCC, c0y = blockIdx.y * TCC;
+  {
+    T v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      const int rr = e / CW, cc = e - rr * CW;
+      const int gy = c0y * K + rr, gx = c0x * K + cc;
+      v[q] = (e < CW * CW && gy < nc && gx < nc) ? ec[(size_t)gy * nc + gx] : T(0);
+    }
+    for (int e = threadIdx.x; e < NT; e += kThreads) sTb[e] = tab[e];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < CW * CW) sC[e] = v[q];
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < CW * FT; it += kThreads) {
+    const int rr = it / FT, l = it - rr * FT;
+    const int cf = l / K, p = l - cf * K, cl = cf >> 1, s2 = cf & 1;  // local coarse cell cl
+    const T* tb = sTb + (s2 * K + p) * (K + 1);
+    const T* src = sC + rr * CW + cl * K;
+    T v = 0;
+#pragma unroll
+    for (int a = 0; a <= K; ++a) v += tb[a] * src[a];
+    sT[it] = v;
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < FT * FT; it += kThreads) {
+    const int m = it / FT, l = it - m * FT;
+    const int fx = 2 * K * c0x + l, fy = 2 * K * c0y + m;
+    if (fx <= 0 || fy <= 0 || fx >= nf - 1 || fy >= nf - 1) continue;
+    const int cf = m / K, p = m - cf * K, cl = cf >> 1, s2 = cf & 1;
+    const T* tb = sTb + (s2 * K + p) * (K + 1);
+    const T* src = sT + (cl * K) * FT + l;
+    T v = 0;
+#pragma unroll
+    for (int a = 0; a <= K; ++a) v += tb[a] * src[a * FT];
+    xf[(size_t)fy * nf + fx] += v;
+  }
+}
+
+template <typename T, int K>
+hipError_t restrict2d_k(int Nc, const T* tab, const T* rf, T* bc, hipStream_t s) {
+  constexpr int TCC = TransferTile2D<K>::TCC;
+  const int nt = (Nc + TCC - 1) / TCC;
+  restrict2d_kernel<T, K, TCC><<<dim3(nt, nt), kThreads, 0, s>>>(rf, bc, Nc, tab);
+  return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t prolong2d_k(int Nc, const T* tab, const T* ec, T* xf, hipStream_t s) {
+  constexpr int TCC = TransferTile2D<K>::TCC;
+  const int nt = (Nc + TCC - 1) / TCC;
+  prolong2d_kernel<T, K, TCC><<<dim3(nt, nt), kThreads, 0, s>>>(ec, xf, Nc, tab);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 template <typename Tin, typename T>
@@ -331,6 +503,24 @@ hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const 
 #undef CALL
 }
 
+template <typename T>
+hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s) {
+#define CALL(K) restrict2d_k<T, K>(Nc, table, rf, bc, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template <typename T>
+hipError_t launch_prolong2d(int k, int Nc, const T* table, const T* ec, T* xf, hipStream_t s) {
+#define CALL(K) prolong2d_k<T, K>(Nc, table, ec, xf, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template hipError_t launch_restrict2d<double>(int, int, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_restrict2d<float>(int, int, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_prolong2d<double>(int, int, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_prolong2d<float>(int, int, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_apply2d<double, double>(int, int, const LevelCoef<double>&, const double*,
                                                    const double*, double*, hipStream_t);
 template hipError_t launch_apply2d<float, double>(int, int, const LevelCoef<double>&, const float*,

@@ -269,6 +269,129 @@ __global__ __launch_bounds__(kThreads) void check_finite_kernel(int64_t n, const
   if (bad) atomicOr(flag, 1);
 }
 
+// ---- Arnoldi step with delayed re-orthogonalisation (classical Gram-Schmidt
+// applied twice, the second pass of vector j fused into step j+1).
+//
+// State at step j: final orthonormal V_0..V_{j-1}; lagged vector u (the
+// new direction after one projection, not yet re-orthogonalised); w = A z_j.
+// One reduction gives a = V^T u, c = V^T w, u.u, u.w, w.w; then
+//   s = a, alpha = sqrt(u.u - |s|^2), V_j = (u - V s) / alpha,
+//   h_v = (u.w - s.c) / alpha  (= V_j . w),
+//   u_new = w - V c - V_j h_v = w - V (c - s h_v/alpha) - u h_v/alpha.
+constexpr int kArnGroup = 8;
+
+__global__ __launch_bounds__(kThreads) void arnoldi_dots_kernel(int64_t n, int j, const double* __restrict__ V,
+                                                                int64_t ldv, const double* __restrict__ u,
+                                                                const double* __restrict__ w,
+                                                                double* __restrict__ partial, int nblk) {
+  // partial rows: [0, j): V_i.u ; [j, 2j): V_i.w ; 2j: u.u ; 2j+1: u.w ; 2j+2: w.w
+  __shared__ double red[kThreads / 64][2 * kArnGroup + 3];
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int ngroups = max(1, (j + kArnGroup - 1) / kArnGroup);
+  for (int g = 0; g < ngroups; ++g) {
+    const int i0 = g * kArnGroup;
+    double au[kArnGroup], aw[kArnGroup], e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+    for (int q = 0; q < kArnGroup; ++q) au[q] = aw[q] = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+      const double ui = u[i], wi = w[i];
+      if (g == 0) {
+        e0 += ui * ui;
+        e1 += ui * wi;
+        e2 += wi * wi;
+      }
+#pragma unroll
+      for (int q = 0; q < kArnGroup; ++q)
+        if (i0 + q < j) {
+          const double v = V[(int64_t)(i0 + q) * ldv + i];
+          au[q] += v * ui;
+          aw[q] += v * wi;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kArnGroup; ++q) {
+      const double x = wave_sum(au[q]), y = wave_sum(aw[q]);
+      if (lane == 0) {
+        red[wid][q] = x;
+        red[wid][kArnGroup + q] = y;
+      }
+    }
+    {
+      const double x0 = wave_sum(e0), x1 = wave_sum(e1), x2 = wave_sum(e2);
+      if (lane == 0) {
+        red[wid][2 * kArnGroup] = x0;
+        red[wid][2 * kArnGroup + 1] = x1;
+        red[wid][2 * kArnGroup + 2] = x2;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kArnGroup + 3) {
+      const int t = threadIdx.x;
+      double sum = 0;
+      for (int q = 0; q < kThreads / 64; ++q) sum += red[q][t];
+      int row = -1;
+      if (t < kArnGroup) row = (i0 + t < j) ? i0 + t : -1;
+      else if (t < 2 * kArnGroup) row = (i0 + t - kArnGroup < j) ? j + i0 + t - kArnGroup : -1;
+      else if (g == 0) row = 2 * j + (t - 2 * kArnGroup);
+      if (row >= 0) partial[(int64_t)row * nblk + blockIdx.x] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// One thread: coefficients of the update from the reduced dots d[0..2j+2].
+// coef layout: [0, j): e_i = s_i / alpha ; [j, 2j): f_i = c_i - s_i h_v / alpha ;
+// 2j: 1/alpha ; 2j+1: h_v/alpha ; 2j+2: alpha ; 2j+3: h_v ; 2j+4: |s|^2/u.u
+__global__ void arnoldi_coef_kernel(int j, const double* __restrict__ d, double* __restrict__ coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double ss = 0, sc = 0;
+  for (int i = 0; i < j; ++i) {
+    ss += d[i] * d[i];
+    sc += d[i] * d[j + i];
+  }
+  const double uu = d[2 * j], uw = d[2 * j + 1];
+  const double a2 = uu - ss;
+  const double alpha = a2 > 0 ? sqrt(a2) : 0.0;
+  const double inv = alpha > 0 ? 1.0 / alpha : 0.0;
+  const double hv = (uw - sc) * inv;
+  for (int i = 0; i < j; ++i) {
+    coef[i] = d[i] * inv;
+    coef[j + i] = d[j + i] - d[i] * hv * inv;
+  }
+  coef[2 * j] = inv;
+  coef[2 * j + 1] = hv * inv;
+  coef[2 * j + 2] = alpha;
+  coef[2 * j + 3] = hv;
+  coef[2 * j + 4] = uu > 0 ? ss / uu : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void arnoldi_update_kernel(int64_t n, int j, const double* __restrict__ V,
+                                                                  int64_t ldv, double* __restrict__ u,
+                                                                  const double* __restrict__ w,
+                                                                  const double* __restrict__ coef,
+                                                                  double* __restrict__ vout) {
+  __shared__ double se[kMaxDot], sf[kMaxDot];
+  for (int t = threadIdx.x; t < j; t += kThreads) {
+    se[t] = coef[t];
+    sf[t] = coef[j + t];
+  }
+  __syncthreads();
+  const double inv = coef[2 * j], d = coef[2 * j + 1];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    const double ui = u[i], wi = w[i];
+    double sv = 0, sw = 0;
+    for (int q = 0; q < j; ++q) {
+      const double v = V[(int64_t)q * ldv + i];
+      sv += se[q] * v;
+      sw += sf[q] * v;
+    }
+    vout[i] = ui * inv - sv;
+    u[i] = wi - sw - d * ui;
+  }
+}
+
 }  // namespace
 
 int multidot_blocks(int64_t n) {
@@ -293,6 +416,7 @@ hipError_t launch_patch_smooth(int dim, int k, int N, const LevelEig<T>& e, cons
 
 template <typename T>
 hipError_t launch_restrict(int dim, int k, int Nc, const T* table, const T* rf, T* bc, T* scratch, hipStream_t s) {
+  if (dim == 2) return launch_restrict2d<T>(k, Nc, table, rf, bc, s);
 #define CALL(K) restrict_k<T, K>(dim, Nc, table, rf, bc, scratch, s)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
@@ -301,6 +425,7 @@ hipError_t launch_restrict(int dim, int k, int Nc, const T* table, const T* rf, 
 template <typename T>
 hipError_t launch_prolong_add(int dim, int k, int Nc, const T* table, const T* ec, T* xf, T* scratch,
                               hipStream_t s) {
+  if (dim == 2) return launch_prolong2d<T>(k, Nc, table, ec, xf, s);
 #define CALL(K) prolong_k<T, K>(dim, Nc, table, ec, xf, scratch, s)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
@@ -357,6 +482,23 @@ template <typename Tz>
 hipError_t launch_update_solution(int64_t n, int m, const Tz* Z, int64_t ldz, const double* y, double* x,
                                   hipStream_t s) {
   update_solution_kernel<Tz><<<grid_for(n), kThreads, 0, s>>>(n, m, Z, ldz, y, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, const double* u, const double* w,
+                               double* partial, int nblk, hipStream_t s) {
+  arnoldi_dots_kernel<<<nblk, kThreads, 0, s>>>(n, j, V, ldv, u, w, partial, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_arnoldi_coef(int j, const double* d, double* coef, hipStream_t s) {
+  arnoldi_coef_kernel<<<1, 64, 0, s>>>(j, d, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_arnoldi_update(int64_t n, int j, const double* V, int64_t ldv, double* u, const double* w,
+                                 const double* coef, double* vout, hipStream_t s) {
+  arnoldi_update_kernel<<<grid_for(n), kThreads, 0, s>>>(n, j, V, ldv, u, w, coef, vout);
   return hipGetLastError();
 }
 

@@ -103,7 +103,8 @@ def test_smoother_f32_matches_oracle(dim, k, N):
     assert rel_l2(host(x0), ref0) <= 1e-5
 
 
-@pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 5, 8), (2, 7, 4)])
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 5, 8), (2, 7, 4), (2, 2, 64), (2, 3, 64),
+                                     (2, 5, 32), (2, 7, 16)])
 def test_vcycle_f64_matches_oracle(dim, k, N):
     say("vcycle f64", dim, k, N)
     H = O.Hierarchy(dim, k, N, omega=0.25)
@@ -116,7 +117,7 @@ def test_vcycle_f64_matches_oracle(dim, k, N):
     assert rel_l2(host(xd), ref) <= 10 * fp64_tol(dim, k, N)
 
 
-@pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16)])
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 3, 64), (2, 4, 32)])
 def test_vcycle_f32_matches_oracle(dim, k, N):
     say("vcycle f32", dim, k, N)
     H = O.Hierarchy(dim, k, N, omega=0.25)
