@@ -439,7 +439,8 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   c0ip_status result = C0IP_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr, ef = nullptr;
   try {
-    const int nblk = c0ip::multidot_blocks(n);
+    const int nblk = std::max(c0ip::multidot_blocks(n), c0ip::arnoldi_blocks(n));
+    const int nblk_a = c0ip::arnoldi_blocks(n);
     p->V.alloc((size_t)m * n);
     p->w.alloc(n);
     p->r64.alloc(n);
@@ -514,8 +515,8 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
         (void)Zp;
         (void)zf32;
         // one reduction: V^T u, V^T w, u.u, u.w, w.w; coefficients on the device
-        p->check(c0ip::launch_arnoldi_dots(n, j, p->V.p, n, p->u.p, p->w.p, p->partial.p, nblk, s), "dots");
-        p->check(c0ip::launch_reduce_partials(2 * j + 3, nblk, p->partial.p, p->hdev.p, 0, s), "reduce");
+        p->check(c0ip::launch_arnoldi_dots(n, j, p->V.p, n, p->u.p, p->w.p, p->partial.p, nblk_a, s), "dots");
+        p->check(c0ip::launch_reduce_partials(2 * j + 3, nblk_a, p->partial.p, p->hdev.p, 0, s), "reduce");
         p->check(c0ip::launch_arnoldi_coef(j, p->hdev.p, p->coef.p, s), "coef");
         p->check(hipMemcpyAsync(hh, p->hdev.p, (2 * j + 3) * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
         p->check(hipMemcpyAsync(hh + 2 * m + 3, p->coef.p, (2 * j + 5) * sizeof(double), hipMemcpyDeviceToHost, s),

@@ -74,6 +74,7 @@ int multidot_blocks(int64_t n);
 // Arnoldi step with delayed re-orthogonalisation (see kernels_common.hip).
 // dots: partial[(2j+3) * nblk]; coef: one thread, writes 2j+5 values;
 // update: V_j = (u - V s)/alpha into vout, u <- w - V f - (h_v/alpha) u.
+int arnoldi_blocks(int64_t n);
 hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, const double* u, const double* w,
                                double* partial, int nblk, hipStream_t s);
 hipError_t launch_arnoldi_coef(int j, const double* d, double* coef, hipStream_t s);

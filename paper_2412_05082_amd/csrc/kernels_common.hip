@@ -280,62 +280,79 @@ __global__ __launch_bounds__(kThreads) void check_finite_kernel(int64_t n, const
 //   u_new = w - V c - V_j h_v = w - V (c - s h_v/alpha) - u h_v/alpha.
 constexpr int kArnGroup = 8;
 
+// Each block owns kArnChunk consecutive entries: u and w stay in registers
+// (kArnPer per lane) while the basis vectors stream past, four at a time.
+constexpr int kArnPer = 8;
+constexpr int kArnChunk = kThreads * kArnPer;
+constexpr int kArnVec = 4;
+
 __global__ __launch_bounds__(kThreads) void arnoldi_dots_kernel(int64_t n, int j, const double* __restrict__ V,
                                                                 int64_t ldv, const double* __restrict__ u,
                                                                 const double* __restrict__ w,
                                                                 double* __restrict__ partial, int nblk) {
   // partial rows: [0, j): V_i.u ; [j, 2j): V_i.w ; 2j: u.u ; 2j+1: u.w ; 2j+2: w.w
-  __shared__ double red[kThreads / 64][2 * kArnGroup + 3];
-  const int64_t chunk = (n + nblk - 1) / nblk;
-  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  __shared__ double red[kThreads / 64][2 * kArnVec];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int ngroups = max(1, (j + kArnGroup - 1) / kArnGroup);
-  for (int g = 0; g < ngroups; ++g) {
-    const int i0 = g * kArnGroup;
-    double au[kArnGroup], aw[kArnGroup], e0 = 0, e1 = 0, e2 = 0;
+  const int64_t base = (int64_t)blockIdx.x * kArnChunk + threadIdx.x;
+  double ur[kArnPer], wr[kArnPer];
+  double e0 = 0, e1 = 0, e2 = 0;
 #pragma unroll
-    for (int q = 0; q < kArnGroup; ++q) au[q] = aw[q] = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-      const double ui = u[i], wi = w[i];
-      if (g == 0) {
-        e0 += ui * ui;
-        e1 += ui * wi;
-        e2 += wi * wi;
-      }
+  for (int e = 0; e < kArnPer; ++e) {
+    const int64_t i = base + (int64_t)e * kThreads;
+    ur[e] = i < n ? u[i] : 0.0;
+    wr[e] = i < n ? w[i] : 0.0;
+    e0 += ur[e] * ur[e];
+    e1 += ur[e] * wr[e];
+    e2 += wr[e] * wr[e];
+  }
+  {
+    const double x0 = wave_sum(e0), x1 = wave_sum(e1), x2 = wave_sum(e2);
+    if (lane == 0) {
+      red[wid][0] = x0;
+      red[wid][1] = x1;
+      red[wid][2] = x2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      double sum = 0;
+      for (int q = 0; q < kThreads / 64; ++q) sum += red[q][threadIdx.x];
+      partial[(int64_t)(2 * j + threadIdx.x) * nblk + blockIdx.x] = sum;
+    }
+    __syncthreads();
+  }
+  for (int i0 = 0; i0 < j; i0 += kArnVec) {
+    double au[kArnVec], aw[kArnVec];
 #pragma unroll
-      for (int q = 0; q < kArnGroup; ++q)
-        if (i0 + q < j) {
-          const double v = V[(int64_t)(i0 + q) * ldv + i];
-          au[q] += v * ui;
-          aw[q] += v * wi;
+    for (int q = 0; q < kArnVec; ++q) {
+      au[q] = aw[q] = 0;
+      if (i0 + q < j) {
+        const double* vq = V + (int64_t)(i0 + q) * ldv;
+#pragma unroll
+        for (int e = 0; e < kArnPer; ++e) {
+          const int64_t i = base + (int64_t)e * kThreads;
+          const double v = i < n ? vq[i] : 0.0;
+          au[q] += v * ur[e];
+          aw[q] += v * wr[e];
         }
+      }
     }
 #pragma unroll
-    for (int q = 0; q < kArnGroup; ++q) {
+    for (int q = 0; q < kArnVec; ++q) {
       const double x = wave_sum(au[q]), y = wave_sum(aw[q]);
       if (lane == 0) {
         red[wid][q] = x;
-        red[wid][kArnGroup + q] = y;
-      }
-    }
-    {
-      const double x0 = wave_sum(e0), x1 = wave_sum(e1), x2 = wave_sum(e2);
-      if (lane == 0) {
-        red[wid][2 * kArnGroup] = x0;
-        red[wid][2 * kArnGroup + 1] = x1;
-        red[wid][2 * kArnGroup + 2] = x2;
+        red[wid][kArnVec + q] = y;
       }
     }
     __syncthreads();
-    if (threadIdx.x < 2 * kArnGroup + 3) {
-      const int t = threadIdx.x;
-      double sum = 0;
-      for (int q = 0; q < kThreads / 64; ++q) sum += red[q][t];
-      int row = -1;
-      if (t < kArnGroup) row = (i0 + t < j) ? i0 + t : -1;
-      else if (t < 2 * kArnGroup) row = (i0 + t - kArnGroup < j) ? j + i0 + t - kArnGroup : -1;
-      else if (g == 0) row = 2 * j + (t - 2 * kArnGroup);
-      if (row >= 0) partial[(int64_t)row * nblk + blockIdx.x] = sum;
+    if (threadIdx.x < 2 * kArnVec) {
+      const int t = threadIdx.x, q = t % kArnVec;
+      if (i0 + q < j) {
+        double sum = 0;
+        for (int r = 0; r < kThreads / 64; ++r) sum += red[r][t];
+        const int row = t < kArnVec ? i0 + q : j + i0 + q;
+        partial[(int64_t)row * nblk + blockIdx.x] = sum;
+      }
     }
     __syncthreads();
   }
@@ -373,16 +390,27 @@ __global__ __launch_bounds__(kThreads) void arnoldi_update_kernel(int64_t n, int
                                                                   const double* __restrict__ coef,
                                                                   double* __restrict__ vout) {
   __shared__ double se[kMaxDot], sf[kMaxDot];
-  for (int t = threadIdx.x; t < j; t += kThreads) {
-    se[t] = coef[t];
-    sf[t] = coef[j + t];
+  for (int t = threadIdx.x; t < kMaxDot; t += kThreads) {
+    se[t] = t < j ? coef[t] : 0.0;
+    sf[t] = t < j ? coef[j + t] : 0.0;
   }
   __syncthreads();
   const double inv = coef[2 * j], d = coef[2 * j + 1];
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     const double ui = u[i], wi = w[i];
     double sv = 0, sw = 0;
-    for (int q = 0; q < j; ++q) {
+    int q = 0;
+    for (; q + 4 <= j; q += 4) {
+      double v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t] = V[(int64_t)(q + t) * ldv + i];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        sv += se[q + t] * v[t];
+        sw += sf[q + t] * v[t];
+      }
+    }
+    for (; q < j; ++q) {
       const double v = V[(int64_t)q * ldv + i];
       sv += se[q] * v;
       sw += sf[q] * v;
@@ -485,8 +513,11 @@ hipError_t launch_update_solution(int64_t n, int m, const Tz* Z, int64_t ldz, co
   return hipGetLastError();
 }
 
+int arnoldi_blocks(int64_t n) { return (int)((n + kArnChunk - 1) / kArnChunk); }
+
 hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, const double* u, const double* w,
                                double* partial, int nblk, hipStream_t s) {
+  if ((int64_t)nblk * kArnChunk < n) return hipErrorInvalidValue;
   arnoldi_dots_kernel<<<nblk, kThreads, 0, s>>>(n, j, V, ldv, u, w, partial, nblk);
   return hipGetLastError();
 }
