@@ -1,0 +1,115 @@
+"""GPU parity of the 3D HIP path (through the C ABI) against the CPU oracle:
+operator, smoother, V-cycle and MG-FGMRES on small 3D meshes (several tiles,
+ragged last tiles), and the full-size 3D Q3 128^3 workload on sampled
+outputs from the windowed oracle.  Tolerances as in the 2D tests."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2412_05082_amd as P
+from tests.gpu_util import dev, fp32_tol, fp64_tol, host, oracle_ops, rel_l2, say, vectors
+
+pytestmark = pytest.mark.gpu
+
+SMALL3 = [(3, 2, 2), (3, 2, 4), (3, 2, 8), (3, 3, 4), (3, 3, 8), (3, 4, 4), (3, 5, 2), (3, 6, 2), (3, 7, 2)]
+
+
+@pytest.mark.parametrize("dim,k,N", SMALL3)
+def test_apply_A_3d(dim, k, N):
+    say("3d apply_A", dim, k, N)
+    A, _, _ = oracle_ops(dim, k, N)
+    x, _ = vectors(dim, k, N)
+    pb = P.Problem(dim, N, k)
+    y = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    pb.apply_A(dev(x), y)
+    y32 = torch.empty(x.size, dtype=torch.float32, device="cuda")
+    x32 = x.astype(np.float32)
+    pb.apply_A(dev(x32), y32)
+    torch.cuda.synchronize()
+    assert rel_l2(host(y), A @ x) <= 1e-12
+    assert rel_l2(host(y32), A @ x32.astype(np.float64)) <= 1e-5
+
+
+@pytest.mark.parametrize("dim,k,N", SMALL3)
+@pytest.mark.parametrize("x_is_zero", [False, True])
+def test_smoother_3d(dim, k, N, x_is_zero):
+    say("3d smoother", dim, k, N, x_is_zero)
+    A, blocks, pidx = oracle_ops(dim, k, N)
+    x, b = vectors(dim, k, N)
+    om = 0.1
+    pb = P.Problem(dim, N, k, omega=om)
+    ref = O.avs_apply(A, blocks, pidx, x, b, om, 1, x_is_zero=x_is_zero)
+    xd = dev(x)
+    pb.apply_smoother(dev(b), xd, x_is_zero=x_is_zero)
+    x32, b32 = x.astype(np.float32), b.astype(np.float32)
+    ref32 = O.avs_apply(A, blocks, pidx, x32.astype(np.float64), b32.astype(np.float64), om, 1, x_is_zero=x_is_zero)
+    xd32 = dev(x32)
+    pb.apply_smoother(dev(b32), xd32, x_is_zero=x_is_zero)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xd), ref) <= fp64_tol(dim, k, N)
+    assert rel_l2(host(xd32), ref32) <= (1e-5 if x_is_zero else fp32_tol(dim, k, N))
+
+
+@pytest.mark.parametrize("dim,k,N", [(3, 2, 8), (3, 3, 8), (3, 4, 4)])
+def test_vcycle_3d(dim, k, N):
+    say("3d vcycle", dim, k, N)
+    H = O.Hierarchy(dim, k, N, omega=0.1)
+    _, b = vectors(dim, k, N)
+    ref = H.vcycle(b)
+    pb = P.Problem(dim, N, k, omega=0.1, vcycle_dtype=P.C0IP_F64)
+    xd = torch.empty(b.size, dtype=torch.float64, device="cuda")
+    pb.vcycle(dev(b), xd)
+    b32 = b.astype(np.float32)
+    ref32 = H.vcycle(b32.astype(np.float64))
+    x32 = torch.empty(b.size, dtype=torch.float32, device="cuda")
+    pb.vcycle(dev(b32), x32)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xd), ref) <= 10 * fp64_tol(dim, k, N)
+    assert rel_l2(host(x32), ref32) <= 1e-4
+
+
+@pytest.mark.parametrize("k,N", [(2, 8), (3, 8)])
+def test_solve_3d(k, N):
+    dim = 3
+    say("3d solve", dim, k, N)
+    A = O.assemble(dim, k, N)
+    _, b = vectors(dim, k, N)
+    H = O.Hierarchy(dim, k, N, omega=0.1)
+    xr, info_r = O.fgmres(A, b, H.vcycle, rtol=1e-8, restart=50)
+    for dt in (P.C0IP_F64, P.C0IP_F32):
+        pb = P.Problem(dim, N, k, omega=0.1, vcycle_dtype=dt)
+        xd = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+        info = pb.solve(dev(b), xd, rtol=1e-8)
+        assert info["converged"] == 1
+        if dt == P.C0IP_F64:
+            assert info["iterations"] == info_r["iterations"]
+        else:
+            assert info["iterations"] <= info_r["iterations"] + 2
+        assert np.linalg.norm(b - A @ host(xd)) / np.linalg.norm(b) <= 1.05e-8
+
+
+def test_full_size_3d_q3_128_sampled():
+    """3D Q3, 128^3 cells (57,066,625 DoFs): A x and S(x,b) at sampled DoFs
+    (corners, edges, faces, interior) against the windowed oracle."""
+    dim, k, N = 3, 3, 128
+    say("3d full size", dim, k, N)
+    x, b = vectors(dim, k, N)
+    n1 = k * N + 1
+    pb = P.Problem(dim, N, k, omega=0.1)
+    y = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    pb.apply_A(dev(x), y)
+    xs = dev(x)
+    pb.apply_smoother(dev(b), xs)
+    torch.cuda.synchronize()
+    yh, sh = host(y), host(xs)
+    rng = np.random.default_rng(7)
+    picks = [(1, 1, 1), (n1 - 2, n1 - 2, n1 - 2), (1, n1 // 2, 3), (k, k, k), (2 * k, 2 * k + 1, 5),
+             (n1 // 2, n1 // 2, n1 // 2), (n1 - 1 - k, 3, n1 // 3)]
+    nodes = [i + n1 * (j + n1 * l) for i, j, l in picks] + list(rng.integers(0, n1 ** 3, 1))
+    nodes = np.array(nodes)
+    ya = O.apply_rows_windowed(dim, k, N, x, nodes)
+    assert np.abs(yh[nodes] - ya).max() <= 1e-12 * np.abs(ya).max()
+    sa = O.avs_nodes_windowed(dim, k, N, x, b, 0.1, nodes)
+    assert np.abs(sh[nodes] - sa).max() <= fp64_tol(dim, k, 8) * np.abs(sa).max()
+    assert np.isfinite(yh).all() and np.isfinite(sh).all()
