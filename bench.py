@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--reps", type=int, default=30, help="kernel timing repetitions")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-N", type=int, default=64, help="cells per direction of the oracle sample")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D Q3 128^3 kernel rates")
     ap.add_argument("--only", default=None,
                     choices=["matvec_f64", "smoother_f64", "matvec_f32", "smoother_f32", "copy_f64"],
                     help="run only this kernel's timing loop (for counter collection) and print its ms")
@@ -108,6 +109,36 @@ def cpu_baseline(k, N, omega):
     return {"value": n / dt, "unit": "DoFs/s", "cores": int(threads), "kind": "oracle",
             "sample": f"oracle FGMRES(50)+float64 V-cycle solve to 1e-8, 2D Q{k} {N}x{N} cells ({n} DoFs), "
                       f"{info['iterations']} its, {dt:.2f} s, setup excluded"}
+
+
+def bench_3d(args, torch, P):
+    """3D Q3, 128^3 cells (57,066,625 DoFs): float64 operator, float32 and
+    float64 smoother step, cold buffers (two sets of 456 MB vectors)."""
+    from paper_2412_05082_amd.inputs import seeded_vector
+    dim, k, N = 3, 3, 128
+    dev = torch.device("cuda:0")
+    xn = seeded_vector(dim, k, N, 1)
+    bn = seeded_vector(dim, k, N, 0)
+    n = xn.size
+    pb = P.Problem(dim, N, k, omega=0.1, vcycle_dtype=P.C0IP_F32)
+    x = torch.from_numpy(xn).to(dev)
+    b = torch.from_numpy(bn).to(dev)
+    sets = [(x, torch.zeros(n, dtype=torch.float64, device=dev), b) for _ in range(2)]
+    reps = max(3, args.reps // 5)
+    ms_mv = time_kernel(lambda s: pb.apply_A(s[0], s[1]), sets, reps, torch)
+    ms_sm = time_kernel(lambda s: pb.apply_smoother(s[2], s[1]), sets, reps, torch)
+    x32, b32 = x.float(), b.float()
+    sets32 = [(x32, torch.zeros(n, dtype=torch.float32, device=dev), b32) for _ in range(2)]
+    ms_mv32 = time_kernel(lambda s: pb.apply_A(s[0], s[1]), sets32, reps, torch)
+    ms_sm32 = time_kernel(lambda s: pb.apply_smoother(s[2], s[1]), sets32, reps, torch)
+    del sets, sets32, x, b, x32, b32
+    pb.close()
+    torch.cuda.empty_cache()
+    out = {"workload": "3D Q3 C0IP biharmonic, 128^3 cells, 57,066,625 DoFs", "dofs": n}
+    for name, ms, byt in [("matvec_f64", ms_mv, 16), ("smoother_f64", ms_sm, 24), ("matvec_f32", ms_mv32, 8),
+                          ("smoother_f32", ms_sm32, 12)]:
+        out[name] = {"ms": ms, "dofs_per_s": n / (ms * 1e-3), "alg_GBs": byt * n / (ms * 1e-3) / 1e9}
+    return out
 
 
 def main():
@@ -216,6 +247,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "float32 smoother step S(x,b) (residual + patch solve), 12 B/DoF"},
     }
+    if not args.no_3d:
+        del pmix, p64
+        torch.cuda.empty_cache()
+        out["config_3d_q3_128"] = bench_3d(args, torch, P)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(k, args.cpu_N, args.omega)
     print(json.dumps(out), flush=True)

@@ -128,6 +128,12 @@ c0ip_status c0ip_apply_A(c0ip_problem* p, int level, c0ip_dtype dtype, const voi
 c0ip_status c0ip_apply_smoother(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b, void* x,
                                 int x_is_zero);
 
+/* Out-of-place form of one smoother step: x_out = S(x_in, b), or S(0, b)
+ * when x_in is NULL.  x_out must not overlap b or x_in (in 2D the step
+ * is one fused launch that reads x_in around every tile it writes). */
+c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b, const void* x_in,
+                               void* x_out);
+
 /* x = MG_L(0, b): one V-cycle of Algorithm 1 on the finest level in the
  * given precision (coarse solve in float64), with the options' pre/post
  * steps and damping. */
@@ -139,6 +145,32 @@ c0ip_status c0ip_vcycle(c0ip_problem* p, c0ip_dtype dtype, const void* b, void* 
  * Returns C0IP_NOT_CONVERGED (x = last iterate) if max_iters is reached. */
 c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const double* b, double* x,
                        c0ip_solve_info* info);
+
+/* ---- batched solves (many independent 2D systems, one graph per round) ----
+ * A batch holds n_problems 2D problems (meshes[i]: any n_cells and degree)
+ * with n_rhs[i] right-hand sides each; every (problem, right-hand side) is
+ * one system solved by its own float64 FGMRES with the V-cycle of opts
+ * (shared damping, steps and precision).  Systems of equal degree and
+ * penalty share every V-cycle launch of a level (all their meshes have
+ * 2^(l+1) cells there), the Krylov kernels take per-system descriptors, and
+ * each round -- one Arnoldi step of every unconverged system -- is a single
+ * replay of a captured HIP graph; converged systems are masked off on the
+ * device.  dim must be 2 (C0IP_EUNSUPPORTED otherwise).  hip_stream: the
+ * caller's stream (NULL = default); the batch orders its work after it. */
+typedef struct c0ip_batch c0ip_batch; /* opaque; owned by the library */
+c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, int n_problems,
+                              const c0ip_mg_opts* opts, void* hip_stream, c0ip_batch** out);
+/* Number of systems (sum of n_rhs). */
+c0ip_status c0ip_batch_num_systems(const c0ip_batch* batch, int* n_systems);
+/* Solve every system.  b, x: HOST arrays of n_problems DEVICE pointers;
+ * b[i] (x[i]) holds problem i's n_rhs[i] float64 vectors back to back, each
+ * of num_dofs entries.  infos: NULL or an array of n_systems entries, in
+ * problem order then right-hand-side order.  Synchronous.  Returns
+ * C0IP_NOT_CONVERGED if any system reached max_iters (its x = last
+ * iterate), C0IP_ENAN if any system met a non-finite value. */
+c0ip_status c0ip_batch_solve(c0ip_batch* batch, const c0ip_krylov_opts* opts, const double* const* b,
+                             double* const* x, c0ip_solve_info* infos);
+c0ip_status c0ip_batch_destroy(c0ip_batch* batch);
 
 /* Description of the last error on the calling thread ("" if none). */
 const char* c0ip_last_error(void);

@@ -62,8 +62,15 @@ _SIGS = {
     "c0ip_apply_A": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "c0ip_apply_smoother": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "c0ip_vcycle": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "c0ip_smoother_step": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "c0ip_solve": (C.c_int, [C.c_void_p, C.POINTER(KrylovOpts), C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]),
     "c0ip_last_error": (C.c_char_p, []),
+    "c0ip_batch_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_int), C.c_int, C.POINTER(MgOpts), C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "c0ip_batch_num_systems": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "c0ip_batch_solve": (C.c_int, [C.c_void_p, C.POINTER(KrylovOpts), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.POINTER(SolveInfo)]),
+    "c0ip_batch_destroy": (C.c_int, [C.c_void_p]),
     "c0ip_host_matrices_1d": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "c0ip_host_patch_inverse": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_int),
                                           C.c_void_p]),
@@ -158,6 +165,13 @@ class Problem:
         _check(load_library().c0ip_apply_smoother(self._h, level, d, self._vec(b, level, d),
                                                   self._vec(x, level, d), int(bool(x_is_zero))))
 
+    def smoother_step(self, b, x_in, x_out, level=-1):
+        """x_out = S(x_in, b) (x_in None: S(0, b)); x_out must not overlap b or x_in."""
+        d = _dt(b)
+        xi = None if x_in is None else self._vec(x_in, level, d)
+        _check(load_library().c0ip_smoother_step(self._h, level, d, self._vec(b, level, d), xi,
+                                                 self._vec(x_out, level, d)))
+
     def vcycle(self, b, x):
         d = _dt(b)
         _check(load_library().c0ip_vcycle(self._h, d, self._vec(b, -1, d), self._vec(x, -1, d)))
@@ -171,6 +185,62 @@ class Problem:
             return info.as_dict()
         _check(st)
         return info.as_dict()
+
+
+class Batch:
+    """Owns a c0ip_batch: problems = [(n_cells, degree), ...] (2D), n_rhs per problem."""
+
+    def __init__(self, problems, n_rhs, gamma=0.0, omega=0.25, pre_steps=1, post_steps=1, vcycle_dtype=C0IP_F32,
+                 coarse_mode=0, stream=None):
+        lib = load_library()
+        self.problems = list(problems)
+        self.n_rhs = list(n_rhs)
+        meshes = (MeshDesc * len(self.problems))(*[MeshDesc(2, N, k, gamma) for N, k in self.problems])
+        rhs = (C.c_int * len(self.n_rhs))(*self.n_rhs)
+        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, 0)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        _check(lib.c0ip_batch_create(meshes, rhs, len(self.problems), C.byref(mg), C.c_void_p(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().c0ip_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_systems(self):
+        v = C.c_int()
+        _check(load_library().c0ip_batch_num_systems(self._h, C.byref(v)))
+        return v.value
+
+    def solve(self, bs, xs, rtol=1e-8, max_iters=500, restart=50, x0_is_zero=True, raise_on_nonconv=True):
+        """bs, xs: lists of contiguous float64 device tensors of shape (n_rhs[i], (k N + 1)^2)."""
+        import torch
+        if len(bs) != len(self.problems) or len(xs) != len(self.problems):
+            raise ValueError("one b and one x tensor per problem")
+        for (N, k), r, b, x in zip(self.problems, self.n_rhs, bs, xs):
+            n = (k * N + 1) ** 2
+            for t in (b, x):
+                if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64
+                        or not t.is_contiguous() or t.numel() != r * n):
+                    raise ValueError(f"expected a contiguous float64 device tensor of {r} x {n} entries")
+        bp = (C.c_void_p * len(bs))(*[t.data_ptr() for t in bs])
+        xp = (C.c_void_p * len(xs))(*[t.data_ptr() for t in xs])
+        ns = self.num_systems()
+        infos = (SolveInfo * ns)()
+        opts = KrylovOpts(rtol, max_iters, restart, int(bool(x0_is_zero)))
+        st = load_library().c0ip_batch_solve(self._h, C.byref(opts), bp, xp, infos)
+        if not (st == -4 and not raise_on_nonconv):
+            _check(st)
+        return [infos[i].as_dict() for i in range(ns)]
 
 
 def host_matrices_1d(degree, n_cells, gamma=0.0):

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/c0ip.h"
+#include "internal.h"
 #include "kernels.h"
 #include "setup.h"
 
@@ -108,6 +109,8 @@ struct c0ip_problem {
   template <typename T>
   void smooth(int l, const T* b, T* x, int steps, bool x_is_zero);
   template <typename T>
+  void smooth_from(int l, const T* b, T* from, T* x, int steps);
+  template <typename T>
   void mg_level(int l, const T* b, T* x);
   void check(hipError_t e, const char* what) {
     if (e != hipSuccess) throw HipFail{e, what};
@@ -151,7 +154,9 @@ void c0ip_problem::prepare(int l) {
   w.ready = true;
 }
 
-// steps of the additive smoother on level l (x_is_zero: start from 0).
+// steps of the additive smoother on level l (x_is_zero: start from 0);
+// result in x.  2D steps from a non-zero iterate are fused (residual kept in
+// LDS) and run out of place, alternating between x and the level's r.
 template <typename T>
 void c0ip_problem::smooth(int l, const T* b, T* x, int steps, bool x_is_zero) {
   LevelWork<T>& w = work<T>(l);
@@ -161,13 +166,36 @@ void c0ip_problem::smooth(int l, const T* b, T* x, int steps, bool x_is_zero) {
     if (x_is_zero) check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), x, stream), "fill");
     return;
   }
-  for (int s = 0; s < steps; ++s) {
-    if (s == 0 && x_is_zero) {
-      check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, b, nullptr, x, om, stream), "smoother");
-    } else {
-      check(c0ip::launch_apply<T, T>(dim, k, Nl, w.coef, x, b, w.r.p, stream), "residual");
-      check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, w.r.p, x, x, om, stream), "smoother");
+  int s0 = 0;
+  if (x_is_zero) {
+    check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, b, nullptr, x, om, stream), "smoother");
+    s0 = 1;
+  }
+  smooth_from(l, b, x, x, steps - s0);
+}
+
+// `steps` smoothing steps starting from the iterate in `from`, result in x
+// (from may be x or the level's r buffer).
+template <typename T>
+void c0ip_problem::smooth_from(int l, const T* b, T* from, T* x, int steps) {
+  LevelWork<T>& w = work<T>(l);
+  const int Nl = lv[l]->N;
+  const T om = (T)mg.omega;
+  if (dim == 2) {
+    T* cur = from;
+    T* oth = (from == x) ? w.r.p : x;
+    for (int s = 0; s < steps; ++s) {
+      check(c0ip::launch_avs2d<T>(k, Nl, w.coef, w.eig, cur, b, oth, om, stream), "fused smoother");
+      std::swap(cur, oth);
     }
+    if (cur != x)
+      check(hipMemcpyAsync(x, cur, sizeof(T) * lv[l]->ntot, hipMemcpyDeviceToDevice, stream), "copy");
+    return;
+  }
+  if (from != x) check(hipMemcpyAsync(x, from, sizeof(T) * lv[l]->ntot, hipMemcpyDeviceToDevice, stream), "copy");
+  for (int s = 0; s < steps; ++s) {
+    check(c0ip::launch_apply<T, T>(dim, k, Nl, w.coef, x, b, w.r.p, stream), "residual");
+    check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, w.r.p, x, x, om, stream), "smoother");
   }
 }
 
@@ -189,8 +217,14 @@ void c0ip_problem::mg_level(int l, const T* b, T* x) {
   check(c0ip::launch_apply<T, T>(dim, k, lv[l]->N, w.coef, x, b, w.r.p, stream), "residual");
   check(c0ip::launch_restrict<T>(dim, k, lv[l - 1]->N, w.ptab.p, w.r.p, wc.b.p, w.scratch.p, stream), "restrict");
   mg_level<T>(l - 1, wc.b.p, wc.x.p);
-  check(c0ip::launch_prolong_add<T>(dim, k, lv[l - 1]->N, w.ptab.p, wc.x.p, x, w.scratch.p, stream), "prolong");
-  smooth<T>(l, b, x, mg.post_steps, false);
+  if (dim == 2 && mg.post_steps > 0) {
+    // r_l = x + P e (out of place), then the fused steps bring the result back to x
+    check(c0ip::launch_prolong2d<T>(k, lv[l - 1]->N, w.ptab.p, wc.x.p, x, w.r.p, stream), "prolong");
+    smooth_from<T>(l, b, w.r.p, x, mg.post_steps);
+  } else {
+    check(c0ip::launch_prolong_add<T>(dim, k, lv[l - 1]->N, w.ptab.p, wc.x.p, x, w.scratch.p, stream), "prolong");
+    smooth<T>(l, b, x, mg.post_steps, false);
+  }
 }
 
 namespace {
@@ -213,6 +247,30 @@ c0ip_status check_mesh(const c0ip_mesh_desc* m) {
 int resolve_level(const c0ip_problem* p, int level) { return level < 0 ? p->L : level; }
 
 }  // namespace
+
+template <typename T>
+const c0ip::LevelCoef<T>& c0ip_internal_coef(c0ip_problem* p, int level) {
+  p->prepare<T>(level);
+  return p->work<T>(level).coef;
+}
+template <typename T>
+const c0ip::LevelEig<T>& c0ip_internal_eig(c0ip_problem* p, int level) {
+  p->prepare<T>(level);
+  return p->work<T>(level).eig;
+}
+template <typename T>
+const T* c0ip_internal_ptab(c0ip_problem* p, int level) {
+  p->prepare<T>(level);
+  return p->work<T>(level).ptab.p;
+}
+const double* c0ip_internal_coarse(c0ip_problem* p) { return p->A0inv.p; }
+void c0ip_internal_set_error(const std::string& msg) { g_err = msg; }
+template const c0ip::LevelCoef<double>& c0ip_internal_coef<double>(c0ip_problem*, int);
+template const c0ip::LevelCoef<float>& c0ip_internal_coef<float>(c0ip_problem*, int);
+template const c0ip::LevelEig<double>& c0ip_internal_eig<double>(c0ip_problem*, int);
+template const c0ip::LevelEig<float>& c0ip_internal_eig<float>(c0ip_problem*, int);
+template const double* c0ip_internal_ptab<double>(c0ip_problem*, int);
+template const float* c0ip_internal_ptab<float>(c0ip_problem*, int);
 
 extern "C" {
 
@@ -371,6 +429,41 @@ c0ip_status c0ip_apply_smoother(c0ip_problem* p, int level, c0ip_dtype dtype, co
     } else {
       return fail(C0IP_EINVAL, "bad dtype");
     }
+  } catch (const HipFail& h) {
+    return hip_fail(h);
+  }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b, const void* x_in,
+                               void* x_out) {
+  g_err.clear();
+  if (!p || !b || !x_out) return fail(C0IP_EINVAL, "NULL argument");
+  if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
+  if (x_out == b || x_out == x_in) return fail(C0IP_EINVAL, "x_out must not overlap b or x_in");
+  const int l = resolve_level(p, level);
+  try {
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      p->prepare<T>(l);
+      LevelWork<T>& w = p->work<T>(l);
+      const int Nl = p->lv[l]->N;
+      const T om = (T)p->mg.omega;
+      const T* bb = (const T*)b;
+      const T* xi = (const T*)x_in;
+      T* xo = (T*)x_out;
+      if (!xi) {
+        p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, bb, nullptr, xo, om, p->stream), "smoother");
+      } else if (p->dim == 2) {
+        p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, xi, bb, xo, om, p->stream), "fused smoother");
+      } else {
+        p->check(c0ip::launch_apply<T, T>(p->dim, p->k, Nl, w.coef, xi, bb, w.r.p, p->stream), "residual");
+        p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, w.r.p, xi, xo, om, p->stream), "smoother");
+      }
+    };
+    if (dtype == C0IP_F64) run(double{});
+    else if (dtype == C0IP_F32) run(float{});
+    else return fail(C0IP_EINVAL, "bad dtype");
   } catch (const HipFail& h) {
     return hip_fail(h);
   }

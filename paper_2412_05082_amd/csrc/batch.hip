@@ -1,0 +1,851 @@
+// Batched solves: many independent systems (problems x right-hand sides,
+// uneven sizes and degrees) advance one flexible-GMRES step per round, and
+// every round is one replay of a captured HIP graph.
+//
+// Systems are grouped by (k, gamma); within a group they are ordered by
+// decreasing number of levels L_s, so at level l the systems still present
+// (L_s >= l) form a prefix 0..A_l-1 and every mesh there has N_l = 2^(l+1)
+// cells: each V-cycle step of a group is ONE launch over all its systems
+// (system = blockIdx.z, vectors n_l apart in per-level slot buffers).  A
+// system enters the V-cycle at its own finest level on the way down and
+// leaves there on the way up (Algorithm 1 for each system).  Converged
+// systems are masked off on the device, so the graph never changes.
+// The Krylov kernels take per-system descriptors (sizes differ).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/c0ip.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace c0ip {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPer = 8;                 // entries per lane in the dot kernel
+constexpr int kChunk = kThreads * kPer;  // entries per dot block
+constexpr int kVec = 4;
+constexpr int kMaxM = 64;
+
+struct KrySys {  // one system's Krylov state on the device (host rewrites it every round)
+  double* V;
+  double* u;
+  const double* w;
+  int64_t n;
+  int64_t poff;  // offset of its partial sums
+  int j;
+  int active;
+  int nblk;
+  int pad;
+};
+
+struct CopyDesc {  // dst[i] = src[i], with the element types of mode
+  const void* src;
+  void* dst;
+  int64_t n;
+  int mode;  // 0 f64->f64, 1 f64->f32, 2 f32->f32
+  int active;
+};
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void bdots_kernel(const KrySys* __restrict__ sys, double* __restrict__ partial) {
+  const KrySys d = sys[blockIdx.y];
+  if (!d.active || (int)blockIdx.x >= d.nblk) return;
+  __shared__ double red[kThreads / 64][2 * kVec];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, j = d.j;
+  const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+  double* P = partial + d.poff;
+  double ur[kPer], wr[kPer], e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int64_t i = base + (int64_t)e * kThreads;
+    ur[e] = i < d.n ? d.u[i] : 0.0;
+    wr[e] = i < d.n ? d.w[i] : 0.0;
+    e0 += ur[e] * ur[e];
+    e1 += ur[e] * wr[e];
+    e2 += wr[e] * wr[e];
+  }
+  {
+    const double x0 = wsum(e0), x1 = wsum(e1), x2 = wsum(e2);
+    if (lane == 0) {
+      red[wid][0] = x0;
+      red[wid][1] = x1;
+      red[wid][2] = x2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      double s = 0;
+      for (int q = 0; q < kThreads / 64; ++q) s += red[q][threadIdx.x];
+      P[(int64_t)(2 * j + threadIdx.x) * d.nblk + blockIdx.x] = s;
+    }
+    __syncthreads();
+  }
+  for (int i0 = 0; i0 < j; i0 += kVec) {
+    double au[kVec], aw[kVec];
+#pragma unroll
+    for (int q = 0; q < kVec; ++q) {
+      au[q] = aw[q] = 0;
+      if (i0 + q < j) {
+        const double* vq = d.V + (int64_t)(i0 + q) * d.n;
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+          const int64_t i = base + (int64_t)e * kThreads;
+          const double v = i < d.n ? vq[i] : 0.0;
+          au[q] += v * ur[e];
+          aw[q] += v * wr[e];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kVec; ++q) {
+      const double x = wsum(au[q]), y = wsum(aw[q]);
+      if (lane == 0) {
+        red[wid][q] = x;
+        red[wid][kVec + q] = y;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kVec) {
+      const int t = threadIdx.x, q = t % kVec;
+      if (i0 + q < j) {
+        double s = 0;
+        for (int r = 0; r < kThreads / 64; ++r) s += red[r][t];
+        P[(int64_t)(t < kVec ? i0 + q : j + i0 + q) * d.nblk + blockIdx.x] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// hout[s][row] = sum over the system's blocks; rows 0..2j+2
+__global__ __launch_bounds__(kThreads) void breduce_kernel(const KrySys* __restrict__ sys, int m,
+                                                           const double* __restrict__ partial,
+                                                           double* __restrict__ hout) {
+  const KrySys d = sys[blockIdx.y];
+  const int row = blockIdx.x;
+  if (!d.active || row >= 2 * d.j + 3) return;
+  __shared__ double red[kThreads / 64];
+  const double* P = partial + d.poff + (int64_t)row * d.nblk;
+  double s = 0;
+  for (int b = threadIdx.x; b < d.nblk; b += kThreads) s += P[b];
+  s = wsum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int q = 0; q < kThreads / 64; ++q) t += red[q];
+    hout[(int64_t)blockIdx.y * (2 * m + 3) + row] = t;
+  }
+}
+
+// Update coefficients per system (same formulas as the single-system solve).
+__global__ void bcoef_kernel(const KrySys* __restrict__ sys, int nsys, int m, const double* __restrict__ hout,
+                             double* __restrict__ coef) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys) return;
+  const KrySys d = sys[s];
+  if (!d.active) return;
+  const int j = d.j;
+  const double* h = hout + (int64_t)s * (2 * m + 3);
+  double* c = coef + (int64_t)s * (2 * m + 5);
+  double ss = 0, sc = 0;
+  for (int i = 0; i < j; ++i) {
+    ss += h[i] * h[i];
+    sc += h[i] * h[j + i];
+  }
+  const double uu = h[2 * j], uw = h[2 * j + 1];
+  const double a2 = uu - ss;
+  const double alpha = a2 > 0 ? sqrt(a2) : 0.0;
+  const double inv = alpha > 0 ? 1.0 / alpha : 0.0;
+  const double hv = (uw - sc) * inv;
+  for (int i = 0; i < j; ++i) {
+    c[i] = h[i] * inv;
+    c[j + i] = h[j + i] - h[i] * hv * inv;
+  }
+  c[2 * j] = inv;
+  c[2 * j + 1] = hv * inv;
+  c[2 * j + 2] = alpha;
+  c[2 * j + 3] = hv;
+  c[2 * j + 4] = uu > 0 ? ss / uu : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void bupdate_kernel(const KrySys* __restrict__ sys, int m,
+                                                           const double* __restrict__ coef) {
+  const KrySys d = sys[blockIdx.y];
+  if (!d.active) return;
+  const int j = d.j;
+  const double* c = coef + (int64_t)blockIdx.y * (2 * m + 5);
+  __shared__ double se[kMaxM], sf[kMaxM];
+  for (int t = threadIdx.x; t < kMaxM; t += kThreads) {
+    se[t] = t < j ? c[t] : 0.0;
+    sf[t] = t < j ? c[j + t] : 0.0;
+  }
+  __syncthreads();
+  const double inv = c[2 * j], dd = c[2 * j + 1];
+  double* vout = d.V + (int64_t)j * d.n;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads) {
+    const double ui = d.u[i], wi = d.w[i];
+    double sv = 0, sw = 0;
+    for (int q = 0; q < j; ++q) {
+      const double v = d.V[(int64_t)q * d.n + i];
+      sv += se[q] * v;
+      sw += sf[q] * v;
+    }
+    vout[i] = ui * inv - sv;
+    d.u[i] = wi - sw - dd * ui;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void bcopy_kernel(const CopyDesc* __restrict__ desc) {
+  const CopyDesc d = desc[blockIdx.y];
+  if (!d.active) return;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads) {
+    if (d.mode == 0)
+      ((double*)d.dst)[i] = ((const double*)d.src)[i];
+    else if (d.mode == 1)
+      ((float*)d.dst)[i] = (float)((const double*)d.src)[i];
+    else
+      ((float*)d.dst)[i] = ((const float*)d.src)[i];
+  }
+}
+
+int blocks_for(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 4096);
+}
+
+}  // namespace
+}  // namespace c0ip
+
+using namespace c0ip;
+
+namespace {
+
+thread_local std::string b_err;
+c0ip_status bfail(c0ip_status s, const std::string& m) {
+  b_err = m;
+  c0ip_internal_set_error(m);
+  return s;
+}
+
+struct HErr {
+  hipError_t e;
+  const char* what;
+};
+inline void hchk(hipError_t e, const char* w) {
+  if (e != hipSuccess) throw HErr{e, w};
+}
+
+template <typename T>
+struct Buf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t c) {
+    if (p && c <= n) return;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    hchk(hipMalloc((void**)&p, std::max<size_t>(c, 1) * sizeof(T)), "hipMalloc");
+    n = c;
+  }
+  ~Buf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+struct Sys {  // one (problem, right-hand side)
+  int problem = 0, rhs = 0, group = 0, slot = 0, L = 0, N = 0;
+  int64_t n = 0;
+  const double* b = nullptr;
+  double* x = nullptr;
+  Buf<double> V, u, r;
+  Buf<double> Z64;
+  Buf<float> Z32;
+  // host FGMRES state
+  std::vector<double> H;
+  double bnorm = 0, beta = 0, g0 = 0, last = 0;
+  int j = 0, its = 0, jdone = 0;
+  bool active = true, converged = false, failed = false;
+  double t_done = 0;
+};
+
+struct Group {
+  int k = 0;
+  double gamma = 0;
+  int Lmax = 0;
+  std::vector<int> members;  // system indices, slot order (descending L)
+  std::vector<int> A;        // A[l] = systems with L_s >= l (a prefix of the slots)
+  c0ip_problem* proto = nullptr;  // tables for levels 0..Lmax
+  std::vector<std::unique_ptr<Buf<float>>> x32, b32, r32;
+  std::vector<std::unique_ptr<Buf<double>>> x64, b64, r64;
+  std::vector<std::unique_ptr<Buf<double>>> W;  // A z of systems whose finest level is l
+  Buf<int> mask;
+};
+
+}  // namespace
+
+struct c0ip_batch {
+  int dim = 2;
+  c0ip_mg_opts mg{};
+  hipStream_t user = nullptr, s = nullptr;
+  std::vector<Sys> sys;
+  std::vector<Group> groups;
+  std::vector<int> nrhs;
+  std::vector<c0ip_mesh_desc> meshes;
+  int m = 0;
+  int64_t partial_total = 0;
+  Buf<KrySys> dsys;
+  Buf<CopyDesc> dcin, dcout;
+  Buf<double> partial, hout, coef, ydev;
+  double* hpin = nullptr;
+  KrySys* hsys = nullptr;
+  CopyDesc *hcin = nullptr, *hcout = nullptr;
+  int* hmask = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_m = -1;
+  ~c0ip_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto& g : groups) c0ip_destroy(g.proto);
+    if (hpin) (void)hipHostFree(hpin);
+    if (hsys) (void)hipHostFree(hsys);
+    if (hcin) (void)hipHostFree(hcin);
+    if (hcout) (void)hipHostFree(hcout);
+    if (hmask) (void)hipHostFree(hmask);
+    if (s) (void)hipStreamDestroy(s);
+  }
+
+  template <typename T>
+  void vcycle(Group& g);
+  void record_round();
+};
+
+template <typename T>
+static Buf<T>& lvbuf(Group& g, int which, int l);
+template <>
+Buf<float>& lvbuf<float>(Group& g, int which, int l) {
+  return which == 0 ? *g.x32[l] : (which == 1 ? *g.b32[l] : *g.r32[l]);
+}
+template <>
+Buf<double>& lvbuf<double>(Group& g, int which, int l) {
+  return which == 0 ? *g.x64[l] : (which == 1 ? *g.b64[l] : *g.r64[l]);
+}
+
+// Algorithm 1 for every system of the group at once (see the file comment).
+template <typename T>
+void c0ip_batch::vcycle(Group& g) {
+  const int k = g.k, pre = mg.pre_steps, post = mg.post_steps;
+  const T om = (T)mg.omega;
+  auto n1 = [&](int l) { return (int64_t)(k * (2 << l) + 1) * (k * (2 << l) + 1); };
+  const int* mask = g.mask.p;
+  for (int l = g.Lmax; l >= 1; --l) {
+    const int nA = g.A[l];
+    if (nA == 0) continue;
+    const int Nl = 2 << l;
+    const int64_t nl = n1(l);
+    T *x = lvbuf<T>(g, 0, l).p, *b = lvbuf<T>(g, 1, l).p, *r = lvbuf<T>(g, 2, l).p;
+    const auto& coef = c0ip_internal_coef<T>(g.proto, l);
+    const auto& eig = c0ip_internal_eig<T>(g.proto, l);
+    if (pre == 0) {
+      hchk(launch_fill_t<T>(nA * nl, T(0), x, s), "fill");
+    } else {
+      hchk(launch_patch2d<T>(k, Nl, eig, b, nullptr, x, om, s, nA, nl, mask), "patch");
+      T *cur = x, *oth = r;
+      for (int st = 1; st < pre; ++st) {
+        hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, oth, om, s, nA, nl, mask), "fused smoother");
+        std::swap(cur, oth);
+      }
+      if (cur != x) hchk(hipMemcpyAsync(x, cur, sizeof(T) * nA * nl, hipMemcpyDeviceToDevice, s), "copy");
+    }
+    hchk(launch_apply2d<T, T>(k, Nl, coef, x, b, r, s, nA, nl, mask), "residual");
+    hchk(launch_restrict2d<T>(k, Nl / 2, c0ip_internal_ptab<T>(g.proto, l), r, lvbuf<T>(g, 1, l - 1).p, s, nA, nl,
+                              n1(l - 1), mask),
+         "restrict");
+  }
+  {
+    const int nA = g.A[0];
+    if (mg.coarse_mode == 0)
+      hchk(launch_coarse<T>(2, k, c0ip_internal_coarse(g.proto), lvbuf<T>(g, 1, 0).p, lvbuf<T>(g, 0, 0).p, s, nA,
+                            n1(0), mask),
+           "coarse");
+    else
+      hchk(launch_patch2d<T>(k, 2, c0ip_internal_eig<T>(g.proto, 0), lvbuf<T>(g, 1, 0).p, nullptr,
+                             lvbuf<T>(g, 0, 0).p, T(1), s, nA, n1(0), mask),
+           "coarse smooth");
+  }
+  for (int l = 1; l <= g.Lmax; ++l) {
+    const int nA = g.A[l];
+    if (nA == 0) continue;
+    const int Nl = 2 << l;
+    const int64_t nl = n1(l);
+    T *x = lvbuf<T>(g, 0, l).p, *b = lvbuf<T>(g, 1, l).p, *r = lvbuf<T>(g, 2, l).p;
+    const auto& coef = c0ip_internal_coef<T>(g.proto, l);
+    const auto& eig = c0ip_internal_eig<T>(g.proto, l);
+    // r = x + P e, then fused steps alternate r -> x -> r ...; the result ends in x
+    T* cur = post > 0 ? r : x;
+    hchk(launch_prolong2d<T>(k, Nl / 2, c0ip_internal_ptab<T>(g.proto, l), lvbuf<T>(g, 0, l - 1).p, x, cur, s, nA,
+                             n1(l - 1), nl, mask),
+         "prolong");
+    T* oth = post > 0 ? x : r;
+    for (int st = 0; st < post; ++st) {
+      hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, oth, om, s, nA, nl, mask), "fused smoother");
+      std::swap(cur, oth);
+    }
+    if (cur != x) hchk(hipMemcpyAsync(x, cur, sizeof(T) * nA * nl, hipMemcpyDeviceToDevice, s), "copy");
+  }
+}
+
+// One round for every system: V-cycle inputs, V-cycles, z -> Z_j, A z,
+// one reduction, coefficients, copy of the reductions to the host, update.
+void c0ip_batch::record_round() {
+  const int ns = (int)sys.size();
+  const bool f32 = mg.vcycle_dtype == C0IP_F32;
+  int64_t nmax = 0;
+  int maxblk = 1;
+  for (auto& q : sys) {
+    nmax = std::max(nmax, q.n);
+    maxblk = std::max(maxblk, (int)((q.n + kChunk - 1) / kChunk));
+  }
+  bcopy_kernel<<<dim3(blocks_for(nmax), ns), kThreads, 0, s>>>(dcin.p);
+  hchk(hipGetLastError(), "copy in");
+  for (auto& g : groups) {
+    if (f32)
+      vcycle<float>(g);
+    else
+      vcycle<double>(g);
+  }
+  bcopy_kernel<<<dim3(blocks_for(nmax), ns), kThreads, 0, s>>>(dcout.p);
+  hchk(hipGetLastError(), "copy out");
+  for (auto& g : groups) {
+    for (int l = 1; l <= g.Lmax; ++l) {
+      const int first = (l + 1 <= g.Lmax) ? g.A[l + 1] : 0, cnt = g.A[l] - first;
+      if (cnt <= 0) continue;
+      const int Nl = 2 << l;
+      const int64_t nl = (int64_t)(g.k * Nl + 1) * (g.k * Nl + 1);
+      const auto& c64 = c0ip_internal_coef<double>(g.proto, l);
+      if (f32)
+        hchk(launch_apply2d<float, double>(g.k, Nl, c64, g.x32[l]->p + first * nl, nullptr, g.W[l]->p, s, cnt, nl,
+                                           g.mask.p + first),
+             "A z");
+      else
+        hchk(launch_apply2d<double, double>(g.k, Nl, c64, g.x64[l]->p + first * nl, nullptr, g.W[l]->p, s, cnt, nl,
+                                            g.mask.p + first),
+             "A z");
+    }
+  }
+  bdots_kernel<<<dim3(maxblk, ns), kThreads, 0, s>>>(dsys.p, partial.p);
+  hchk(hipGetLastError(), "dots");
+  breduce_kernel<<<dim3(2 * m + 3, ns), kThreads, 0, s>>>(dsys.p, m, partial.p, hout.p);
+  hchk(hipGetLastError(), "reduce");
+  bcoef_kernel<<<(ns + 63) / 64, 64, 0, s>>>(dsys.p, ns, m, hout.p, coef.p);
+  hchk(hipGetLastError(), "coef");
+  hchk(hipMemcpyAsync(hpin, hout.p, sizeof(double) * ns * (2 * m + 3), hipMemcpyDeviceToHost, s), "D2H");
+  hchk(hipMemcpyAsync(hpin + (size_t)ns * (2 * m + 3), coef.p, sizeof(double) * ns * (2 * m + 5),
+                      hipMemcpyDeviceToHost, s),
+       "D2H");
+  bupdate_kernel<<<dim3(blocks_for(nmax), ns), kThreads, 0, s>>>(dsys.p, m, coef.p);
+  hchk(hipGetLastError(), "update");
+}
+
+static double lsq(const std::vector<double>& H, int m, int j, double g0, std::vector<double>& R,
+                  std::vector<double>& g) {
+  const int nr = j + 2, nc = j + 1;
+  R.assign((size_t)nr * nc, 0.0);
+  for (int r = 0; r < nr; ++r)
+    for (int c = 0; c < nc; ++c) R[(size_t)r * nc + c] = H[(size_t)r * m + c];
+  g.assign(nr, 0.0);
+  g[0] = g0;
+  for (int c = 0; c < nc; ++c) {
+    const double a = R[(size_t)c * nc + c], b = R[(size_t)(c + 1) * nc + c];
+    const double den = std::hypot(a, b);
+    const double cs = den > 0 ? a / den : 1.0, sn = den > 0 ? b / den : 0.0;
+    for (int cc = c; cc < nc; ++cc) {
+      const double x = R[(size_t)c * nc + cc], y = R[(size_t)(c + 1) * nc + cc];
+      R[(size_t)c * nc + cc] = cs * x + sn * y;
+      R[(size_t)(c + 1) * nc + cc] = -sn * x + cs * y;
+    }
+    const double x = g[c], y = g[c + 1];
+    g[c] = cs * x + sn * y;
+    g[c + 1] = -sn * x + cs * y;
+  }
+  return std::fabs(g[nr - 1]);
+}
+
+extern "C" {
+
+c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, int n_problems,
+                              const c0ip_mg_opts* opts, void* hip_stream, c0ip_batch** out) {
+  b_err.clear();
+  if (!out || !meshes || !n_rhs || n_problems < 1) return bfail(C0IP_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  c0ip_mg_opts mg;
+  if (opts) {
+    mg = *opts;
+  } else {
+    mg.omega = 0.25;
+    mg.pre_steps = mg.post_steps = 1;
+    mg.vcycle_dtype = C0IP_F32;
+    mg.coarse_mode = 0;
+    mg.scatter_mode = 0;
+  }
+  std::unique_ptr<c0ip_batch> bt(new c0ip_batch());
+  bt->mg = mg;
+  bt->user = (hipStream_t)hip_stream;
+  try {
+    hchk(hipStreamCreateWithFlags(&bt->s, hipStreamNonBlocking), "stream");
+    // systems
+    for (int i = 0; i < n_problems; ++i) {
+      const c0ip_mesh_desc& md = meshes[i];
+      if (md.dim != 2) return bfail(C0IP_EUNSUPPORTED, "batches are built for 2D meshes");
+      if (n_rhs[i] < 1 || n_rhs[i] > 4096) return bfail(C0IP_EINVAL, "n_rhs must be in [1, 4096]");
+      if (md.degree < 2 || md.degree > 7 || md.n_cells < 2 || (md.n_cells & (md.n_cells - 1)))
+        return bfail(C0IP_EINVAL, "bad mesh in batch");
+      bt->meshes.push_back(md);
+      bt->nrhs.push_back(n_rhs[i]);
+      const double gam = md.gamma > 0 ? md.gamma : (double)(md.degree * (md.degree + 1));
+      int gi = -1;
+      for (size_t q = 0; q < bt->groups.size(); ++q)
+        if (bt->groups[q].k == md.degree && bt->groups[q].gamma == gam) gi = (int)q;
+      if (gi < 0) {
+        bt->groups.emplace_back();
+        bt->groups.back().k = md.degree;
+        bt->groups.back().gamma = gam;
+        gi = (int)bt->groups.size() - 1;
+      }
+      int L = 0;
+      while ((2 << L) < md.n_cells) ++L;
+      for (int r = 0; r < n_rhs[i]; ++r) {
+        Sys q;
+        q.problem = i;
+        q.rhs = r;
+        q.group = gi;
+        q.L = L;
+        q.N = md.n_cells;
+        q.n = (int64_t)(md.degree * md.n_cells + 1) * (md.degree * md.n_cells + 1);
+        bt->sys.push_back(std::move(q));
+        bt->groups[gi].members.push_back((int)bt->sys.size() - 1);
+      }
+    }
+    // groups: slot order, level prefix counts, tables, level slot buffers
+    for (auto& g : bt->groups) {
+      std::stable_sort(g.members.begin(), g.members.end(),
+                       [&](int a, int b) { return bt->sys[a].L > bt->sys[b].L; });
+      g.Lmax = bt->sys[g.members.front()].L;
+      g.A.assign(g.Lmax + 2, 0);
+      for (size_t si = 0; si < g.members.size(); ++si) {
+        Sys& q = bt->sys[g.members[si]];
+        q.slot = (int)si;
+        for (int l = 0; l <= q.L; ++l) g.A[l]++;
+      }
+      c0ip_mesh_desc md{2, 2 << g.Lmax, g.k, g.gamma};
+      c0ip_mg_opts mo = mg;
+      c0ip_status st = c0ip_create(&md, &mo, (void*)bt->s, &g.proto);
+      if (st != C0IP_OK) return st;
+      const bool f32 = mg.vcycle_dtype == C0IP_F32;
+      for (int l = 0; l <= g.Lmax; ++l) {
+        const int64_t nl = (int64_t)(g.k * (2 << l) + 1) * (g.k * (2 << l) + 1);
+        const size_t cnt = (size_t)g.A[l] * nl;
+        if (f32) {
+          g.x32.emplace_back(new Buf<float>());
+          g.b32.emplace_back(new Buf<float>());
+          g.r32.emplace_back(new Buf<float>());
+          g.x32.back()->alloc(cnt);
+          g.b32.back()->alloc(cnt);
+          g.r32.back()->alloc(cnt);
+        } else {
+          g.x64.emplace_back(new Buf<double>());
+          g.b64.emplace_back(new Buf<double>());
+          g.r64.emplace_back(new Buf<double>());
+          g.x64.back()->alloc(cnt);
+          g.b64.back()->alloc(cnt);
+          g.r64.back()->alloc(cnt);
+        }
+        const int fin = g.A[l] - (l + 1 <= g.Lmax ? g.A[l + 1] : 0);
+        g.W.emplace_back(new Buf<double>());
+        g.W.back()->alloc((size_t)std::max(fin, 0) * nl);
+      }
+      g.mask.alloc(g.members.size());
+    }
+  } catch (const HErr& h) {
+    return bfail(C0IP_EHIP, std::string(h.what) + ": " + hipGetErrorString(h.e));
+  } catch (const std::bad_alloc&) {
+    return bfail(C0IP_ENOMEM, "host allocation failed");
+  }
+  *out = bt.release();
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_batch_destroy(c0ip_batch* bt) {
+  delete bt;
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_batch_num_systems(const c0ip_batch* bt, int* n) {
+  if (!bt || !n) return bfail(C0IP_EINVAL, "NULL argument");
+  *n = (int)bt->sys.size();
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_batch_solve(c0ip_batch* bt, const c0ip_krylov_opts* opts, const double* const* b,
+                             double* const* x, c0ip_solve_info* infos) {
+  b_err.clear();
+  if (!bt || !opts || !b || !x) return bfail(C0IP_EINVAL, "NULL argument");
+  if (!(opts->rtol > 0) || opts->max_iters < 1 || opts->restart < 1 || opts->restart > kMaxM)
+    return bfail(C0IP_EINVAL, "bad Krylov options (rtol > 0, max_iters >= 1, restart in [1,64])");
+  const int m = opts->restart, ns = (int)bt->sys.size();
+  const bool f32 = bt->mg.vcycle_dtype == C0IP_F32;
+  hipStream_t s = bt->s;
+  auto t0 = std::chrono::steady_clock::now();
+  c0ip_status result = C0IP_OK;
+  try {
+    for (int i = 0; i < (int)bt->meshes.size(); ++i)
+      if (!b[i] || !x[i]) return bfail(C0IP_EINVAL, "NULL vector in batch");
+    // order after the caller's pending work
+    hipEvent_t ev;
+    hchk(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+    hchk(hipEventRecord(ev, bt->user), "event");
+    hchk(hipStreamWaitEvent(s, ev, 0), "wait");
+    // work space
+    bt->m = m;
+    int64_t poff = 0;
+    for (auto& q : bt->sys) {
+      q.b = b[q.problem] + (size_t)q.rhs * q.n;
+      q.x = x[q.problem] + (size_t)q.rhs * q.n;
+      q.V.alloc((size_t)m * q.n);
+      q.u.alloc(q.n);
+      q.r.alloc(q.n);
+      if (f32) q.Z32.alloc((size_t)m * q.n);
+      else q.Z64.alloc((size_t)m * q.n);
+      q.H.assign((size_t)(m + 1) * m, 0.0);
+      const int nblk = (int)((q.n + kChunk - 1) / kChunk);
+      poff += (int64_t)(2 * m + 3) * nblk;
+    }
+    bt->partial.alloc(poff);
+    bt->hout.alloc((size_t)ns * (2 * m + 3));
+    bt->coef.alloc((size_t)ns * (2 * m + 5));
+    bt->ydev.alloc(kMaxM);
+    bt->dsys.alloc(ns);
+    bt->dcin.alloc(ns);
+    bt->dcout.alloc(ns);
+    if (!bt->hpin) {
+      hchk(hipHostMalloc((void**)&bt->hpin, sizeof(double) * (size_t)ns * (4 * kMaxM + 8)), "pinned");
+      hchk(hipHostMalloc((void**)&bt->hsys, sizeof(KrySys) * ns), "pinned");
+      hchk(hipHostMalloc((void**)&bt->hcin, sizeof(CopyDesc) * ns), "pinned");
+      hchk(hipHostMalloc((void**)&bt->hcout, sizeof(CopyDesc) * ns), "pinned");
+      hchk(hipHostMalloc((void**)&bt->hmask, sizeof(int) * ns), "pinned");
+    }
+    // initial residuals (eager, per system): bnorm over free DoFs, r = b - A x0, u = r / beta
+    auto norm2 = [&](const double* v, int64_t n) {
+      hchk(launch_multidot(n, 1, v, n, v, bt->partial.p, multidot_blocks(n), s), "norm");
+      hchk(launch_reduce_partials(1, multidot_blocks(n), bt->partial.p, bt->hout.p, 0, s), "norm");
+      hchk(hipMemcpyAsync(bt->hpin, bt->hout.p, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+      hchk(hipStreamSynchronize(s), "sync");
+      return bt->hpin[0];
+    };
+    auto residual = [&](Sys& q, const double* xx) {
+      Group& g = bt->groups[q.group];
+      hchk(launch_apply2d<double, double>(g.k, q.N, c0ip_internal_coef<double>(g.proto, q.L), xx, q.b, q.r.p, s),
+           "residual");
+    };
+    auto restart = [&](Sys& q) {
+      hchk(launch_multidot(q.n, 1, q.r.p, q.n, q.r.p, bt->partial.p, multidot_blocks(q.n), s), "norm");
+      hchk(launch_reduce_partials(1, multidot_blocks(q.n), bt->partial.p, bt->hout.p, 0, s), "norm");
+      hchk(launch_normalize(q.n, q.r.p, bt->hout.p, q.u.p, s), "normalize");
+      std::fill(q.H.begin(), q.H.end(), 0.0);
+      q.j = 0;
+      q.g0 = q.beta;
+    };
+    for (auto& q : bt->sys) {
+      hchk(launch_fill(q.n, 0.0, q.u.p, s), "fill");
+      residual(q, q.u.p);  // b with boundary entries ignored
+      q.bnorm = std::sqrt(norm2(q.r.p, q.n));
+      if (opts->x0_is_zero) hchk(launch_fill(q.n, 0.0, q.x, s), "fill");
+      else residual(q, q.x);
+      q.beta = std::sqrt(norm2(q.r.p, q.n));
+      q.its = 0;
+      q.converged = q.bnorm == 0.0 || q.beta <= opts->rtol * q.bnorm;
+      q.active = !q.converged;
+      q.failed = !std::isfinite(q.bnorm) || !std::isfinite(q.beta);
+      if (q.failed) q.active = false;
+      q.last = q.beta;
+      if (q.active) restart(q);
+    }
+    // descriptors that do not change between rounds
+    int64_t off = 0;
+    for (int i = 0; i < ns; ++i) {
+      Sys& q = bt->sys[i];
+      Group& g = bt->groups[q.group];
+      const int nblk = (int)((q.n + kChunk - 1) / kChunk);
+      const int first = (q.L + 1 <= g.Lmax) ? g.A[q.L + 1] : 0;
+      KrySys& d = bt->hsys[i];
+      d.V = q.V.p;
+      d.u = q.u.p;
+      d.w = g.W[q.L]->p + (int64_t)(q.slot - first) * q.n;
+      d.n = q.n;
+      d.poff = off;
+      d.nblk = nblk;
+      d.pad = 0;
+      off += (int64_t)(2 * m + 3) * nblk;
+      CopyDesc& ci = bt->hcin[i];
+      ci.src = q.u.p;
+      ci.dst = f32 ? (void*)(g.b32[q.L]->p + (int64_t)q.slot * q.n) : (void*)(g.b64[q.L]->p + (int64_t)q.slot * q.n);
+      ci.n = q.n;
+      ci.mode = f32 ? 1 : 0;
+      CopyDesc& co = bt->hcout[i];
+      co.src = f32 ? (const void*)(g.x32[q.L]->p + (int64_t)q.slot * q.n)
+                   : (const void*)(g.x64[q.L]->p + (int64_t)q.slot * q.n);
+      co.n = q.n;
+      co.mode = f32 ? 2 : 0;
+    }
+    // capture one round (graph reused while m is unchanged)
+    if (!bt->exec || bt->graph_m != m) {
+      if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+      if (bt->graph) (void)hipGraphDestroy(bt->graph);
+      bt->exec = nullptr;
+      bt->graph = nullptr;
+      hchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "capture");
+      try {
+        bt->record_round();
+      } catch (...) {
+        hipGraph_t tmp;
+        (void)hipStreamEndCapture(s, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+      }
+      hchk(hipStreamEndCapture(s, &bt->graph), "capture");
+      hchk(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0), "instantiate");
+      bt->graph_m = m;
+    }
+    std::vector<double> R, gg, y(m);
+    for (;;) {
+      int nact = 0;
+      for (int i = 0; i < ns; ++i) {
+        Sys& q = bt->sys[i];
+        KrySys& d = bt->hsys[i];
+        d.j = q.j;
+        d.active = q.active ? 1 : 0;
+        bt->hcin[i].active = d.active;
+        bt->hcout[i].active = d.active;
+        bt->hcout[i].dst = f32 ? (void*)(q.Z32.p + (size_t)q.j * q.n) : (void*)(q.Z64.p + (size_t)q.j * q.n);
+        nact += d.active;
+      }
+      if (nact == 0) break;
+      hchk(hipMemcpyAsync(bt->dsys.p, bt->hsys, sizeof(KrySys) * ns, hipMemcpyHostToDevice, s), "H2D");
+      hchk(hipMemcpyAsync(bt->dcin.p, bt->hcin, sizeof(CopyDesc) * ns, hipMemcpyHostToDevice, s), "H2D");
+      hchk(hipMemcpyAsync(bt->dcout.p, bt->hcout, sizeof(CopyDesc) * ns, hipMemcpyHostToDevice, s), "H2D");
+      {
+        int off = 0;
+        for (auto& g : bt->groups) {
+          for (size_t si = 0; si < g.members.size(); ++si)
+            bt->hmask[off + si] = bt->sys[g.members[si]].active ? 1 : 0;
+          hchk(hipMemcpyAsync(g.mask.p, bt->hmask + off, sizeof(int) * g.members.size(), hipMemcpyHostToDevice, s),
+               "H2D");
+          off += (int)g.members.size();
+        }
+      }
+      hchk(hipGraphLaunch(bt->exec, s), "graph launch");
+      hchk(hipStreamSynchronize(s), "sync");
+      const double* hh = bt->hpin;
+      const double* cc = bt->hpin + (size_t)ns * (2 * m + 3);
+      for (int i = 0; i < ns; ++i) {
+        Sys& q = bt->sys[i];
+        if (!q.active) continue;
+        const int j = q.j;
+        const double* d = hh + (size_t)i * (2 * m + 3);
+        const double* cf = cc + (size_t)i * (2 * m + 5);
+        const double alpha = cf[2 * j + 2], hv = cf[2 * j + 3];
+        if (!std::isfinite(alpha) || !std::isfinite(hv) || !std::isfinite(d[2 * j + 2])) {
+          q.failed = true;
+          q.active = false;
+          continue;
+        }
+        if (j == 0) {
+          q.g0 = q.beta * alpha;
+        } else {
+          for (int t = 0; t < j; ++t) q.H[(size_t)t * m + (j - 1)] += d[t];
+          q.H[(size_t)j * m + (j - 1)] = alpha;
+        }
+        double c2 = 0;
+        for (int t = 0; t < j; ++t) {
+          q.H[(size_t)t * m + j] = d[j + t];
+          c2 += d[j + t] * d[j + t];
+        }
+        q.H[(size_t)j * m + j] = hv;
+        const double ww = d[2 * j + 2];
+        double est2 = ww - c2 - hv * hv;
+        if (!(est2 > 1e-10 * ww)) est2 = norm2(q.u.p, q.n);
+        q.H[(size_t)(j + 1) * m + j] = std::sqrt(std::max(est2, 0.0));
+        const double res = lsq(q.H, m, j, q.g0, R, gg);
+        q.its++;
+        q.last = res;
+        const bool conv = res <= opts->rtol * q.bnorm || q.H[(size_t)(j + 1) * m + j] == 0.0;
+        if (conv || j + 1 == m || q.its >= opts->max_iters) {
+          // x += Z y, new residual; restart or stop
+          const int jd = j + 1;
+          lsq(q.H, m, j, q.g0, R, gg);
+          for (int t = jd - 1; t >= 0; --t) {
+            double v = gg[t];
+            for (int l2 = t + 1; l2 < jd; ++l2) v -= R[(size_t)t * jd + l2] * y[l2];
+            y[t] = v / R[(size_t)t * jd + t];
+          }
+          hchk(hipMemcpyAsync(bt->ydev.p, y.data(), jd * sizeof(double), hipMemcpyHostToDevice, s), "H2D");
+          if (f32)
+            hchk(launch_update_solution<float>(q.n, jd, q.Z32.p, q.n, bt->ydev.p, q.x, s), "update x");
+          else
+            hchk(launch_update_solution<double>(q.n, jd, q.Z64.p, q.n, bt->ydev.p, q.x, s), "update x");
+          residual(q, q.x);
+          q.beta = std::sqrt(norm2(q.r.p, q.n));
+          if (conv) {
+            q.converged = true;
+            q.active = false;
+          } else if (q.its >= opts->max_iters) {
+            q.active = false;
+          } else {
+            restart(q);
+          }
+        } else {
+          q.j = j + 1;
+        }
+      }
+    }
+    hchk(hipStreamSynchronize(s), "sync");
+    (void)hipEventDestroy(ev);
+    auto t1 = std::chrono::steady_clock::now();
+    const double secs = std::chrono::duration<double>(t1 - t0).count();
+    bool all = true, anynan = false;
+    for (int i = 0; i < ns; ++i) {
+      Sys& q = bt->sys[i];
+      all = all && q.converged;
+      anynan = anynan || q.failed || !std::isfinite(q.beta);
+      if (infos) {
+        c0ip_solve_info& inf = infos[i];
+        inf = c0ip_solve_info{};
+        inf.iterations = q.its;
+        inf.converged = q.converged ? 1 : 0;
+        inf.rel_res_est = q.bnorm > 0 ? q.last / q.bnorm : 0.0;
+        inf.rel_res_true = q.bnorm > 0 ? q.beta / q.bnorm : 0.0;
+        inf.frac_iters =
+            (q.its > 0 && inf.rel_res_est > 0) ? 8.0 * q.its / (-std::log10(inf.rel_res_est)) : 0.0;
+        inf.seconds_total = secs;
+      }
+    }
+    if (anynan) result = bfail(C0IP_ENAN, "non-finite value in a batched system");
+    else if (!all) result = bfail(C0IP_NOT_CONVERGED, "some systems reached max_iters");
+  } catch (const HErr& h) {
+    (void)hipStreamSynchronize(s);
+    result = bfail(C0IP_EHIP, std::string(h.what) + ": " + hipGetErrorString(h.e));
+  }
+  return result;
+}
+
+}  // extern "C"

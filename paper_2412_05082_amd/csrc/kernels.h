@@ -41,9 +41,11 @@ template <typename T>
 hipError_t launch_prolong_add(int dim, int k, int Nc, const T* table, const T* ec, T* xf, T* scratch,
                               hipStream_t s);
 
-// Level-0 solve: x = A0^{-1} b on the (2k-1)^dim interior nodes (float64).
+// Level-0 solve: x = A0^{-1} b on the (2k-1)^dim interior nodes (float64);
+// batched over nsys systems zs apart, skipping those with active[z] == 0.
 template <typename T>
-hipError_t launch_coarse(int dim, int k, const double* Ainv, const T* b, T* x, hipStream_t s);
+hipError_t launch_coarse(int dim, int k, const double* Ainv, const T* b, T* x, hipStream_t s, int nsys = 1,
+                         int64_t zs = 0, const int* active = nullptr);
 
 // Vector kernels (n = length).
 template <typename Ta, typename Tb>
@@ -82,15 +84,26 @@ hipError_t launch_arnoldi_update(int64_t n, int j, const double* V, int64_t ldv,
                                  const double* coef, double* vout, hipStream_t s);
 
 // Per-dimension operator and smoother launchers (k dispatched at run time).
+// Batched forms (2D): nsys systems whose vectors are zs elements apart
+// (fine / coarse strides zf / zc for the transfers); nsys = 1 for one.
 template <typename Tin, typename T>
-hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s);
+hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s,
+                          int nsys = 1, int64_t zs = 0, const int* active = nullptr);
 template <typename T>
 hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
-                          hipStream_t s);
+                          hipStream_t s, int nsys = 1, int64_t zs = 0, const int* active = nullptr);
+// One fused smoothing step S(x, b) (residual in LDS, x_out may alias x only
+// if every tile reads x before any tile writes: it may NOT alias).
 template <typename T>
-hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s);
+hipError_t launch_avs2d(int k, int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout,
+                        T omega, hipStream_t s, int nsys = 1, int64_t zs = 0, const int* active = nullptr);
 template <typename T>
-hipError_t launch_prolong2d(int k, int Nc, const T* table, const T* ec, T* xf, hipStream_t s);
+hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s, int nsys = 1,
+                             int64_t zf = 0, int64_t zc = 0, const int* active = nullptr);
+// xf = xin + P ec (xin may equal xf)
+template <typename T>
+hipError_t launch_prolong2d(int k, int Nc, const T* table, const T* ec, const T* xin, T* xf, hipStream_t s,
+                            int nsys = 1, int64_t zc = 0, int64_t zf = 0, const int* active = nullptr);
 template <typename Tin, typename T>
 hipError_t launch_apply3d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s);
 template <typename T>

@@ -56,7 +56,7 @@ __device__ __forceinline__ void x_sweeps(const T* __restrict__ sX, T* __restrict
     const bool vw = (r >= K) && (r < RY - K);
 #pragma unroll
     for (int p = 0; p < K; ++p) {
-      const int g = min(x0 + cc * K + p, n1 - 1);
+      const int g = max(0, min(x0 + cc * K + p, n1 - 1));
       const int cls = INTERIOR ? (2 * left + p) : row_class(g, n1, K, left, right0, periodic);
       const T* cM = tab + (size_t)cls * W + H;
       const T* cL = tab + (size_t)(nclass + cls) * W + H;
@@ -131,9 +131,15 @@ template <int K> __host__ __device__ constexpr int tab_max() { return 3 * (5 * K
 template <typename Tin, typename T, int K, int TXC, int TYC, bool RES>
 __global__ __launch_bounds__(kThreads) void apply2d_kernel(const Tin* __restrict__ x, const T* __restrict__ b,
                                                            T* __restrict__ y, int n1, const T* __restrict__ tab,
-                                                           int nclass, int left, int right0, int periodic) {
+                                                           int nclass, int left, int right0, int periodic,
+                                                           int64_t zs, const int* __restrict__ active) {
   constexpr int H = 2 * K, TX = TXC * K, TY = TYC * K, RX = TX + 2 * H, RY = TY + 2 * H;
   constexpr int NL = (RY * RX + kThreads - 1) / kThreads;
+  if (active && !active[blockIdx.z]) return;
+  // system blockIdx.z of a batch of equally sized vectors zs apart
+  x += blockIdx.z * zs;
+  y += blockIdx.z * zs;
+  if (RES) b += blockIdx.z * zs;
   __shared__ T sX[RY * RX];
   __shared__ T sU[RY * TX];
   __shared__ T sV[(TY + 2 * K) * TX];
@@ -185,16 +191,17 @@ template <> struct ApplyTile2D<6> { static constexpr int TXC = 4, TYC = 4; };
 template <> struct ApplyTile2D<7> { static constexpr int TXC = 4, TYC = 4; };
 
 template <typename Tin, typename T, int K>
-hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s) {
+hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s, int nsys,
+                     int64_t zs, const int* active) {
   constexpr int TXC = ApplyTile2D<K>::TXC, TYC = ApplyTile2D<K>::TYC;
   const int n1 = K * N + 1;
-  dim3 grid((n1 + TXC * K - 1) / (TXC * K), (n1 + TYC * K - 1) / (TYC * K));
+  dim3 grid((n1 + TXC * K - 1) / (TXC * K), (n1 + TYC * K - 1) / (TYC * K), nsys);
   if (b)
     apply2d_kernel<Tin, T, K, TXC, TYC, true><<<grid, kThreads, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left,
-                                                                        c.right0, c.periodic);
+                                                                        c.right0, c.periodic, zs, active);
   else
     apply2d_kernel<Tin, T, K, TXC, TYC, false><<<grid, kThreads, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left,
-                                                                         c.right0, c.periodic);
+                                                                         c.right0, c.periodic, zs, active);
   return hipGetLastError();
 }
 
@@ -206,8 +213,12 @@ template <typename T, int K, int TC>
 __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__ r, const T* __restrict__ xin,
                                                            T* __restrict__ xout, int N, int n1,
                                                            const T* __restrict__ Qg, const T* __restrict__ lamg,
-                                                           T omega) {
+                                                           T omega, int64_t zs, const int* __restrict__ active) {
   constexpr int n = 2 * K - 1, NN = n * n, NP = TC + 1, S = (TC + 2) * K - 1;
+  if (active && !active[blockIdx.z]) return;
+  r += blockIdx.z * zs;
+  xout += blockIdx.z * zs;
+  if (xin) xin += blockIdx.z * zs;
   constexpr int NL = (S * S + kThreads - 1) / kThreads;
   __shared__ T sR[S * S];
   __shared__ T sA[NP * NP * NN];
@@ -332,6 +343,246 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
   }
 }
 
+// ------------------------------------------------------------------ fused smoother
+// One step S(x, b) = x + omega sum_v R_v^T A~_v^{-1} R_v (b - A x) in one
+// launch: the residual is computed on the owned tile extended by one cell
+// (the support of every patch touching the tile) with the operator's
+// sweeps, kept in LDS, and consumed by the patch solves; r never goes to
+// HBM.  Tile TC x TC owned cells; the residual tile is (TC+2) x (TC+2)
+// cells starting one cell before the owned one.
+
+template <typename T, int K, int TXC, int TYC, bool INTERIOR>
+__device__ __forceinline__ void y_sweeps_residual_lds(const T* __restrict__ sU, const T* __restrict__ sV,
+                                                      const T* __restrict__ sW, int x0, int y0, int n1,
+                                                      const T* __restrict__ tab, int nclass, int left, int right0,
+                                                      int periodic, const T* __restrict__ b, T* __restrict__ sRr) {
+  constexpr int H = 2 * K, TX = TXC * K, W = 4 * K + 1;
+  for (int it = threadIdx.x; it < TX * TYC; it += kThreads) {
+    const int cr = it / TX, l = it - cr * TX;
+    const int gx = x0 + l;
+    T u[4 * K + 1], v[2 * K + 1], w[2 * K + 1];
+#pragma unroll
+    for (int j = 0; j <= 4 * K; ++j) u[j] = sU[(cr * K + j) * TX + l];
+#pragma unroll
+    for (int j = 0; j <= 2 * K; ++j) {
+      v[j] = sV[(cr * K + j) * TX + l];
+      w[j] = sW[(cr * K + j) * TX + l];
+    }
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      const int gy = y0 + cr * K + p;
+      const int cls = INTERIOR ? (2 * left + p) : row_class(max(0, min(gy, n1 - 1)), n1, K, left, right0, periodic);
+      const T* cM = tab + (size_t)cls * W + H;
+      const T* cL = tab + (size_t)(nclass + cls) * W + H;
+      const T* cB = tab + (size_t)(2 * nclass + cls) * W + H;
+      T am = 0, al = 0, ab = 0;
+#pragma unroll
+      for (int o = m_lo<K>(p); o <= m_hi<K>(p); ++o) {
+        am += cM[o] * w[p + o + K];
+        al += cL[o] * v[p + o + K];
+      }
+#pragma unroll
+      for (int o = b_lo<K>(p); o <= b_hi<K>(p); ++o) ab += cB[o] * u[p + o + H];
+      const bool inner = gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2;
+      sRr[(cr * K + p) * TX + l] = inner ? b[(size_t)gy * n1 + gx] - (am + 2 * al + ab) : T(0);
+    }
+  }
+}
+
+// Patch solves of the fused smoother.  Interior tiles (every patch of
+// variant 0) index Q and lambda with loop-invariant addresses, so the
+// eigenbasis stays in registers across the items of a thread.
+template <typename T, int K, int TC, bool INTERIOR>
+__device__ __forceinline__ void fused_patches(const T* __restrict__ sRr, T* __restrict__ pool,
+                                              const T* __restrict__ Q, const T* __restrict__ lam, int N, int cx0,
+                                              int cy0) {
+  constexpr int TX = (TC + 2) * K, n = 2 * K - 1, NN = n * n, NP = TC + 1;
+  T* sA = pool;
+  T* sB = pool + NP * NP * NN;
+  // patch solves, as in patch2d_kernel; the residual tile node of patch (vx,vy),
+  // entry (a, c), is ((vy - cy0) K + 1 + a, (vx - cx0) K + 1 + c)
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, a = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = cx0 + pxl, vy = cy0 + pyl;
+    if (!INTERIOR && (vx < 1 || vx > N - 1 || vy < 1 || vy > N - 1)) continue;
+    const T* q = INTERIOR ? Q : Q + variant(vx, N) * NN;
+    T in[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) in[c] = sRr[(pyl * K + 1 + a) * TX + pxl * K + 1 + c];
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int cp = 0; cp < n; ++cp) s += q[cp * n + c] * in[cp];
+      sA[p * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, c = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = cx0 + pxl, vy = cy0 + pyl;
+    if (!INTERIOR && (vx < 1 || vx > N - 1 || vy < 1 || vy > N - 1)) continue;
+    const int ty = INTERIOR ? 0 : variant(vy, N), tx = INTERIOR ? 0 : variant(vx, N);
+    const T* q = Q + ty * NN;
+    const T lx = lam[tx * n + c];
+    T col[n], t[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) col[a] = sA[p * NN + a * n + c];
+#pragma unroll
+    for (int ap = 0; ap < n; ++ap) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) s += q[a * n + ap] * col[a];
+      t[ap] = s / (lx + lam[ty * n + ap]);
+    }
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int ap = 0; ap < n; ++ap) s += q[a * n + ap] * t[ap];
+      sB[p * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, a = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = cx0 + pxl, vy = cy0 + pyl;
+    if (!INTERIOR && (vx < 1 || vx > N - 1 || vy < 1 || vy > N - 1)) continue;
+    const T* q = INTERIOR ? Q : Q + variant(vx, N) * NN;
+    T in[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) in[c] = sB[p * NN + a * n + c];
+#pragma unroll
+    for (int cp = 0; cp < n; ++cp) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < n; ++c) s += q[cp * n + c] * in[c];
+      sA[p * NN + a * n + cp] = s;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int K, int TC>
+__global__ __launch_bounds__(kThreads) void avs2d_kernel(const T* __restrict__ x, const T* __restrict__ b,
+                                                         T* __restrict__ xout, int N, int n1,
+                                                         const T* __restrict__ tab, int nclass, int left,
+                                                         int right0, int periodic, const T* __restrict__ Qg,
+                                                         const T* __restrict__ lamg, T omega, int64_t zs,
+                                                         const int* __restrict__ active) {
+  constexpr int TXC = TC + 2, TYC = TC + 2, H = 2 * K, TX = TXC * K, TY = TYC * K, RX = TX + 2 * H,
+                RY = TY + 2 * H;
+  constexpr int n = 2 * K - 1, NN = n * n, NP = TC + 1;
+  constexpr int SZA = RY * RX + RY * TX + 2 * (TY + 2 * K) * TX, SZB = 2 * NP * NP * NN;
+  constexpr int NL = (RY * RX + kThreads - 1) / kThreads;
+  __shared__ T pool[SZA > SZB ? SZA : SZB];
+  __shared__ T sRr[TY * TX];
+  __shared__ T sTab[tab_max<K>()];
+  __shared__ T sQ[4 * NN];
+  __shared__ T sLam[4 * n];
+  if (active && !active[blockIdx.z]) return;
+  x += blockIdx.z * zs;
+  b += blockIdx.z * zs;
+  xout += blockIdx.z * zs;
+  const int cx0 = blockIdx.x * TC, cy0 = blockIdx.y * TC;
+  const int x0 = (cx0 - 1) * K, y0 = (cy0 - 1) * K;  // residual tile origin (a vertex node)
+  T* sX = pool;
+  T* sU = sX + RY * RX;
+  T* sV = sU + RY * TX;
+  T* sW = sV + (TY + 2 * K) * TX;
+  {
+    T v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      const int r = e / RX, c = e - r * RX;
+      const int gy = y0 - H + r, gx = x0 - H + c;
+      v[q] = (e < RY * RX && gy >= 0 && gy < n1 && gx >= 0 && gx < n1) ? x[(size_t)gy * n1 + gx] : T(0);
+    }
+    const int ntab = 3 * nclass * (4 * K + 1);
+    for (int e = threadIdx.x; e < ntab; e += kThreads) sTab[e] = tab[e];
+    for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
+    for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < RY * RX) sX[e] = v[q];
+    }
+  }
+  __syncthreads();
+  const bool xin = periodic && x0 >= left && x0 + TX <= right0;
+  const bool yin = periodic && y0 >= left && y0 + TY <= right0;
+  if (xin)
+    x_sweeps<T, K, TXC, TYC, true>(sX, sU, sV, sW, x0, n1, tab, nclass, left, right0, periodic);
+  else
+    x_sweeps<T, K, TXC, TYC, false>(sX, sU, sV, sW, x0, n1, sTab, nclass, left, right0, periodic);
+  __syncthreads();
+  if (yin)
+    y_sweeps_residual_lds<T, K, TXC, TYC, true>(sU, sV, sW, x0, y0, n1, tab, nclass, left, right0, periodic, b,
+                                                sRr);
+  else
+    y_sweeps_residual_lds<T, K, TXC, TYC, false>(sU, sV, sW, x0, y0, n1, sTab, nclass, left, right0, periodic, b,
+                                                 sRr);
+  __syncthreads();
+  // all patches of the tile interior (vertices in [2, N-2]): one eigenbasis
+  const bool interior = cx0 >= 2 && cx0 + TC <= N - 2 && cy0 >= 2 && cy0 + TC <= N - 2;
+  T* sA = pool;
+  if (interior)
+    fused_patches<T, K, TC, true>(sRr, pool, sQ, sLam, N, cx0, cy0);
+  else
+    fused_patches<T, K, TC, false>(sRr, pool, sQ, sLam, N, cx0, cy0);
+  constexpr int OW = TC * K + 1;
+  const int gx0 = cx0 * K, gy0 = cy0 * K;
+  const int gx1 = (cx0 + TC >= N) ? n1 : (cx0 + TC) * K;
+  const int gy1 = (cy0 + TC >= N) ? n1 : (cy0 + TC) * K;
+  for (int e = threadIdx.x; e < OW * OW; e += kThreads) {
+    const int jj = e / OW, ii = e - jj * OW;
+    const int gx = gx0 + ii, gy = gy0 + jj;
+    if (gx >= gx1 || gy >= gy1) continue;
+    const size_t idx = (size_t)gy * n1 + gx;
+    if (gx == 0 || gx == n1 - 1 || gy == 0 || gy == n1 - 1) {
+      xout[idx] = T(0);
+      continue;
+    }
+    const int vxa = gx / K, vxb = (gx % K == 0) ? vxa : vxa + 1;
+    const int vya = gy / K, vyb = (gy % K == 0) ? vya : vya + 1;
+    T acc = 0;
+    for (int vy = vya; vy <= vyb; ++vy) {
+      if (vy < 1 || vy > N - 1) continue;
+      for (int vx = vxa; vx <= vxb; ++vx) {
+        if (vx < 1 || vx > N - 1) continue;
+        const int p = (vy - cy0) * NP + (vx - cx0);
+        const int c = gx - ((vx - 1) * K + 1), a = gy - ((vy - 1) * K + 1);
+        acc += sA[p * NN + a * n + c];
+      }
+    }
+    xout[idx] = x[idx] + omega * acc;
+  }
+}
+
+template <int K> struct FusedTile2D;
+template <> struct FusedTile2D<2> { static constexpr int TC = 16; };
+template <> struct FusedTile2D<3> { static constexpr int TC = 8; };
+template <> struct FusedTile2D<4> { static constexpr int TC = 8; };
+template <> struct FusedTile2D<5> { static constexpr int TC = 4; };
+template <> struct FusedTile2D<6> { static constexpr int TC = 4; };
+template <> struct FusedTile2D<7> { static constexpr int TC = 4; };
+
+template <typename T, int K>
+hipError_t avs2d_k(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout, T omega,
+                   hipStream_t s, int nsys, int64_t zs, const int* active) {
+  constexpr int TC = FusedTile2D<K>::TC;
+  const int n1 = K * N + 1;
+  const int nt = (N + TC - 1) / TC;
+  avs2d_kernel<T, K, TC><<<dim3(nt, nt, nsys), kThreads, 0, s>>>(x, b, xout, N, n1, c.tab, c.nclass, c.left,
+                                                                 c.right0, c.periodic, e.Q, e.lam, omega, zs,
+                                                                 active);
+  return hipGetLastError();
+}
+
 template <int K> struct PatchTile2D;
 template <> struct PatchTile2D<2> { static constexpr int TC = 16; };
 template <> struct PatchTile2D<3> { static constexpr int TC = 8; };
@@ -341,12 +592,13 @@ template <> struct PatchTile2D<6> { static constexpr int TC = 4; };
 template <> struct PatchTile2D<7> { static constexpr int TC = 4; };
 
 template <typename T, int K>
-hipError_t patch2d_k(int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega, hipStream_t s) {
+hipError_t patch2d_k(int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega, hipStream_t s,
+                     int nsys, int64_t zs, const int* active) {
   constexpr int TC = PatchTile2D<K>::TC;
   const int n1 = K * N + 1;
   const int nt = (N + TC - 1) / TC;
-  dim3 grid(nt, nt);
-  patch2d_kernel<T, K, TC><<<grid, kThreads, 0, s>>>(r, xin, xout, N, n1, e.Q, e.lam, omega);
+  dim3 grid(nt, nt, nsys);
+  patch2d_kernel<T, K, TC><<<grid, kThreads, 0, s>>>(r, xin, xout, N, n1, e.Q, e.lam, omega, zs, active);
   return hipGetLastError();
 }
 
@@ -361,8 +613,12 @@ template <int K> struct TransferTile2D { static constexpr int TCC = K <= 4 ? 8 :
 
 template <typename T, int K, int TCC>
 __global__ __launch_bounds__(kThreads) void restrict2d_kernel(const T* __restrict__ rf, T* __restrict__ bc, int Nc,
-                                                              const T* __restrict__ tab) {
+                                                              const T* __restrict__ tab, int64_t zf, int64_t zc,
+                                                              const int* __restrict__ active) {
   constexpr int CT = TCC * K, F = 2 * K * (TCC + 1), NT = 2 * K * (K + 1);
+  if (active && !active[blockIdx.z]) return;
+  rf += blockIdx.z * zf;
+  bc += blockIdx.z * zc;
   constexpr int NL = (F * F + kThreads - 1) / kThreads;
   __shared__ T sF[F * F];
   __shared__ T sT[F * CT];
@@ -419,9 +675,14 @@ __global__ __launch_bounds__(kThreads) void restrict2d_kernel(const T* __restric
 }
 
 template <typename T, int K, int TCC>
-__global__ __launch_bounds__(kThreads) void prolong2d_kernel(const T* __restrict__ ec, T* __restrict__ xf, int Nc,
-                                                             const T* __restrict__ tab) {
+__global__ __launch_bounds__(kThreads) void prolong2d_kernel(const T* __restrict__ ec, const T* xin, T* xf, int Nc,
+                                                             const T* __restrict__ tab, int64_t zc, int64_t zf,
+                                                             const int* __restrict__ active) {
   constexpr int CW = TCC * K + 1, FT = 2 * K * TCC, NT = 2 * K * (K + 1);
+  if (active && !active[blockIdx.z]) return;
+  ec += blockIdx.z * zc;
+  xf += blockIdx.z * zf;
+  xin += blockIdx.z * zf;
   constexpr int NL = (CW * CW + kThreads - 1) / kThreads;
   __shared__ T sC[CW * CW];
   __shared__ T sT[CW * FT];
@@ -456,80 +717,109 @@ __global__ __launch_bounds__(kThreads) void prolong2d_kernel(const T* __restrict
     sT[it] = v;
   }
   __syncthreads();
-  for (int it = threadIdx.x; it < FT * FT; it += kThreads) {
-    const int m = it / FT, l = it - m * FT;
+  // fine nodes [2k c0, 2k (c0 + TCC)) of this tile, plus the last (boundary)
+  // node of the mesh for the last tile, so that every output is written
+  constexpr int FO = FT + 1;
+  for (int it = threadIdx.x; it < FO * FO; it += kThreads) {
+    const int m = it / FO, l = it - m * FO;
     const int fx = 2 * K * c0x + l, fy = 2 * K * c0y + m;
-    if (fx <= 0 || fy <= 0 || fx >= nf - 1 || fy >= nf - 1) continue;
+    if (fx >= nf || fy >= nf) continue;
+    if ((l == FT && fx != nf - 1) || (m == FT && fy != nf - 1)) continue;
+    const size_t idx = (size_t)fy * nf + fx;
+    if (fx == 0 || fy == 0 || fx == nf - 1 || fy == nf - 1) {
+      xf[idx] = T(0);
+      continue;
+    }
     const int cf = m / K, p = m - cf * K, cl = cf >> 1, s2 = cf & 1;
     const T* tb = sTb + (s2 * K + p) * (K + 1);
     const T* src = sT + (cl * K) * FT + l;
     T v = 0;
 #pragma unroll
     for (int a = 0; a <= K; ++a) v += tb[a] * src[a * FT];
-    xf[(size_t)fy * nf + fx] += v;
+    xf[idx] = xin[idx] + v;
   }
 }
 
 template <typename T, int K>
-hipError_t restrict2d_k(int Nc, const T* tab, const T* rf, T* bc, hipStream_t s) {
+hipError_t restrict2d_k(int Nc, const T* tab, const T* rf, T* bc, hipStream_t s, int nsys, int64_t zf,
+                        int64_t zc, const int* active) {
   constexpr int TCC = TransferTile2D<K>::TCC;
   const int nt = (Nc + TCC - 1) / TCC;
-  restrict2d_kernel<T, K, TCC><<<dim3(nt, nt), kThreads, 0, s>>>(rf, bc, Nc, tab);
+  restrict2d_kernel<T, K, TCC><<<dim3(nt, nt, nsys), kThreads, 0, s>>>(rf, bc, Nc, tab, zf, zc, active);
   return hipGetLastError();
 }
 
 template <typename T, int K>
-hipError_t prolong2d_k(int Nc, const T* tab, const T* ec, T* xf, hipStream_t s) {
+hipError_t prolong2d_k(int Nc, const T* tab, const T* ec, const T* xin, T* xf, hipStream_t s, int nsys,
+                       int64_t zc, int64_t zf, const int* active) {
   constexpr int TCC = TransferTile2D<K>::TCC;
   const int nt = (Nc + TCC - 1) / TCC;
-  prolong2d_kernel<T, K, TCC><<<dim3(nt, nt), kThreads, 0, s>>>(ec, xf, Nc, tab);
+  prolong2d_kernel<T, K, TCC><<<dim3(nt, nt, nsys), kThreads, 0, s>>>(ec, xin, xf, Nc, tab, zc, zf, active);
   return hipGetLastError();
 }
 
 }  // namespace
 
 template <typename Tin, typename T>
-hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s) {
-#define CALL(K) apply2d_k<Tin, T, K>(N, c, x, b, y, s)
+hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s,
+                          int nsys, int64_t zs, const int* active) {
+#define CALL(K) apply2d_k<Tin, T, K>(N, c, x, b, y, s, nsys, zs, active)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
 
 template <typename T>
 hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
-                          hipStream_t s) {
-#define CALL(K) patch2d_k<T, K>(N, e, r, xin, xout, omega, s)
+                          hipStream_t s, int nsys, int64_t zs, const int* active) {
+#define CALL(K) patch2d_k<T, K>(N, e, r, xin, xout, omega, s, nsys, zs, active)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
 
 template <typename T>
-hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s) {
-#define CALL(K) restrict2d_k<T, K>(Nc, table, rf, bc, s)
+hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s, int nsys,
+                             int64_t zf, int64_t zc, const int* active) {
+#define CALL(K) restrict2d_k<T, K>(Nc, table, rf, bc, s, nsys, zf, zc, active)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
 
 template <typename T>
-hipError_t launch_prolong2d(int k, int Nc, const T* table, const T* ec, T* xf, hipStream_t s) {
-#define CALL(K) prolong2d_k<T, K>(Nc, table, ec, xf, s)
+hipError_t launch_prolong2d(int k, int Nc, const T* table, const T* ec, const T* xin, T* xf, hipStream_t s,
+                            int nsys, int64_t zc, int64_t zf, const int* active) {
+#define CALL(K) prolong2d_k<T, K>(Nc, table, ec, xin, xf, s, nsys, zc, zf, active)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
 
-template hipError_t launch_restrict2d<double>(int, int, const double*, const double*, double*, hipStream_t);
-template hipError_t launch_restrict2d<float>(int, int, const float*, const float*, float*, hipStream_t);
-template hipError_t launch_prolong2d<double>(int, int, const double*, const double*, double*, hipStream_t);
-template hipError_t launch_prolong2d<float>(int, int, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_restrict2d<double>(int, int, const double*, const double*, double*, hipStream_t, int,
+                                              int64_t, int64_t, const int*);
+template hipError_t launch_restrict2d<float>(int, int, const float*, const float*, float*, hipStream_t, int, int64_t,
+                                             int64_t, const int*);
+template hipError_t launch_prolong2d<double>(int, int, const double*, const double*, const double*, double*,
+                                             hipStream_t, int, int64_t, int64_t, const int*);
+template hipError_t launch_prolong2d<float>(int, int, const float*, const float*, const float*, float*, hipStream_t,
+                                            int, int64_t, int64_t, const int*);
+template <typename T>
+hipError_t launch_avs2d(int k, int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout,
+                        T omega, hipStream_t s, int nsys, int64_t zs, const int* active) {
+#define CALL(K) avs2d_k<T, K>(N, c, e, x, b, xout, omega, s, nsys, zs, active)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+template hipError_t launch_avs2d<double>(int, int, const LevelCoef<double>&, const LevelEig<double>&, const double*,
+                                         const double*, double*, double, hipStream_t, int, int64_t, const int*);
+template hipError_t launch_avs2d<float>(int, int, const LevelCoef<float>&, const LevelEig<float>&, const float*,
+                                        const float*, float*, float, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_apply2d<double, double>(int, int, const LevelCoef<double>&, const double*,
-                                                   const double*, double*, hipStream_t);
+                                                   const double*, double*, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_apply2d<float, double>(int, int, const LevelCoef<double>&, const float*,
-                                                  const double*, double*, hipStream_t);
+                                                  const double*, double*, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_apply2d<float, float>(int, int, const LevelCoef<float>&, const float*, const float*,
-                                                 float*, hipStream_t);
+                                                 float*, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_patch2d<double>(int, int, const LevelEig<double>&, const double*, const double*,
-                                           double*, double, hipStream_t);
+                                           double*, double, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_patch2d<float>(int, int, const LevelEig<float>&, const float*, const float*, float*,
-                                          float, hipStream_t);
+                                          float, hipStream_t, int, int64_t, const int*);
 
 }  // namespace c0ip

@@ -127,7 +127,11 @@ hipError_t prolong_k(int dim, int Nc, const T* tab, const T* ec, T* xf, T* scrat
 // on the interior, 0 on the boundary.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void coarse_kernel(int dim, int k, const double* __restrict__ Ainv,
-                                                          const T* __restrict__ b, T* __restrict__ x) {
+                                                          const T* __restrict__ b, T* __restrict__ x, int64_t zs,
+                                                          const int* __restrict__ active) {
+  if (active && !active[blockIdx.y]) return;
+  b += blockIdx.y * zs;
+  x += blockIdx.y * zs;
   const int n1 = 2 * k + 1, n = 2 * k - 1;
   const int ntot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
   const int n0 = dim == 2 ? n * n : n * n * n;
@@ -453,16 +457,17 @@ hipError_t launch_restrict(int dim, int k, int Nc, const T* table, const T* rf, 
 template <typename T>
 hipError_t launch_prolong_add(int dim, int k, int Nc, const T* table, const T* ec, T* xf, T* scratch,
                               hipStream_t s) {
-  if (dim == 2) return launch_prolong2d<T>(k, Nc, table, ec, xf, s);
+  if (dim == 2) return launch_prolong2d<T>(k, Nc, table, ec, xf, xf, s);
 #define CALL(K) prolong_k<T, K>(dim, Nc, table, ec, xf, scratch, s)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
 
 template <typename T>
-hipError_t launch_coarse(int dim, int k, const double* Ainv, const T* b, T* x, hipStream_t s) {
+hipError_t launch_coarse(int dim, int k, const double* Ainv, const T* b, T* x, hipStream_t s, int nsys, int64_t zs,
+                         const int* active) {
   const int n1 = 2 * k + 1, ntot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
-  coarse_kernel<T><<<(ntot + kThreads - 1) / kThreads, kThreads, 0, s>>>(dim, k, Ainv, b, x);
+  coarse_kernel<T><<<dim3((ntot + kThreads - 1) / kThreads, nsys), kThreads, 0, s>>>(dim, k, Ainv, b, x, zs, active);
   return hipGetLastError();
 }
 
@@ -555,8 +560,10 @@ template hipError_t launch_prolong_add<double>(int, int, int, const double*, con
                                                hipStream_t);
 template hipError_t launch_prolong_add<float>(int, int, int, const float*, const float*, float*, float*,
                                               hipStream_t);
-template hipError_t launch_coarse<double>(int, int, const double*, const double*, double*, hipStream_t);
-template hipError_t launch_coarse<float>(int, int, const double*, const float*, float*, hipStream_t);
+template hipError_t launch_coarse<double>(int, int, const double*, const double*, double*, hipStream_t, int, int64_t,
+                                          const int*);
+template hipError_t launch_coarse<float>(int, int, const double*, const float*, float*, hipStream_t, int, int64_t,
+                                         const int*);
 template hipError_t launch_cast<double, float>(int64_t, const double*, float*, hipStream_t);
 template hipError_t launch_cast<float, double>(int64_t, const float*, double*, hipStream_t);
 template hipError_t launch_fill_t<float>(int64_t, float, float*, hipStream_t);

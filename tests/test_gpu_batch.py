@@ -1,0 +1,102 @@
+"""Batched solves (many uneven 2D systems, one captured graph per round)
+against the eager single-system solve of each system: equal iteration
+counts and solutions, over two consecutive batched solves (every round is
+a graph replay; restarts and finalisations run eagerly in between)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2412_05082_amd as P
+from paper_2412_05082_amd.inputs import seeded_vector
+from tests.gpu_util import host, say
+
+pytestmark = pytest.mark.gpu
+
+PROBLEMS = [(16, 2), (8, 3), (32, 3), (16, 4), (4, 2), (64, 2), (8, 4)]
+NRHS = [2, 1, 3, 1, 1, 1, 2]
+
+
+def _rhs(N, k, r, seed0):
+    return np.stack([seeded_vector(2, k, N, seed0 + q) for q in range(r)])
+
+
+@pytest.mark.parametrize("dtype", [P.C0IP_F32, P.C0IP_F64])
+def test_batch_matches_single_solves(dtype):
+    say("batch vs single", dtype)
+    bt = P.Batch(PROBLEMS, NRHS, omega=0.25, vcycle_dtype=dtype)
+    assert bt.num_systems() == sum(NRHS)
+    bs = [torch.from_numpy(_rhs(N, k, r, 100 * i)).cuda() for i, ((N, k), r) in enumerate(zip(PROBLEMS, NRHS))]
+    for rep in range(2):
+        xs = [torch.zeros_like(b) for b in bs]
+        infos = bt.solve(bs, xs, rtol=1e-8, restart=50)
+        torch.cuda.synchronize()
+        t = 0
+        for i, ((N, k), r) in enumerate(zip(PROBLEMS, NRHS)):
+            pb = P.Problem(2, N, k, omega=0.25, vcycle_dtype=dtype)
+            A = O.assemble(2, k, N) if N <= 32 else None
+            for q in range(r):
+                b = bs[i][q].contiguous()
+                xref = torch.zeros_like(b)
+                info = pb.solve(b, xref, rtol=1e-8)
+                assert infos[t]["converged"] == 1, (i, q, infos[t])
+                assert infos[t]["iterations"] == info["iterations"], (i, q, infos[t], info)
+                xb, xr = host(xs[i][q]), host(xref)
+                assert np.linalg.norm(xb - xr) <= 1e-10 * np.linalg.norm(xr), (i, q)
+                if A is not None:
+                    bh = host(b)
+                    assert np.linalg.norm(bh - A @ xb) <= 1.05e-8 * np.linalg.norm(bh)
+                t += 1
+
+
+def test_batch_two_smoothing_steps():
+    say("batch 2+2 steps")
+    probs, nrhs = [(32, 3), (8, 2)], [2, 1]
+    bt = P.Batch(probs, nrhs, omega=0.25, pre_steps=2, post_steps=2)
+    bs = [torch.from_numpy(_rhs(N, k, r, 11 * i)).cuda() for i, ((N, k), r) in enumerate(zip(probs, nrhs))]
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = bt.solve(bs, xs)
+    t = 0
+    for i, ((N, k), r) in enumerate(zip(probs, nrhs)):
+        pb = P.Problem(2, N, k, omega=0.25, pre_steps=2, post_steps=2)
+        for q in range(r):
+            xr = torch.zeros_like(bs[i][q])
+            info = pb.solve(bs[i][q].contiguous(), xr)
+            assert infos[t]["iterations"] == info["iterations"]
+            assert np.linalg.norm(host(xs[i][q]) - host(xr)) <= 1e-10 * np.linalg.norm(host(xr))
+            t += 1
+
+
+def test_batch_restart_and_max_iters():
+    say("batch restart")
+    probs, nrhs = [(16, 2), (8, 3)], [1, 2]
+    bt = P.Batch(probs, nrhs, omega=0.25)
+    bs = [torch.from_numpy(_rhs(N, k, r, 7 * i + 1)).cuda() for i, ((N, k), r) in enumerate(zip(probs, nrhs))]
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = bt.solve(bs, xs, rtol=1e-8, restart=5)  # several restarts per system
+    assert all(inf["converged"] == 1 for inf in infos)
+    t = 0
+    for i, ((N, k), r) in enumerate(zip(probs, nrhs)):
+        A = O.assemble(2, k, N)
+        for q in range(r):
+            bh, xh = host(bs[i][q]), host(xs[i][q])
+            assert np.linalg.norm(bh - A @ xh) <= 1.05e-8 * np.linalg.norm(bh)
+            t += 1
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = bt.solve(bs, xs, rtol=1e-8, restart=50, max_iters=2, raise_on_nonconv=False)
+    assert all(inf["iterations"] == 2 and inf["converged"] == 0 for inf in infos)
+
+
+def test_batch_rejects_3d_and_bad_shapes():
+    lib = P.load_library()
+    with pytest.raises(P.C0ipError):
+        P.Batch([(8, 1)], [1])
+    bt = P.Batch([(8, 2)], [2])
+    with pytest.raises(ValueError):
+        bt.solve([torch.zeros(17 * 17, dtype=torch.float64, device="cuda")],
+                 [torch.zeros(17 * 17, dtype=torch.float64, device="cuda")])
+    import ctypes as C
+    meshes = (P.MeshDesc * 1)(P.MeshDesc(3, 4, 2, 0.0))
+    rhs = (C.c_int * 1)(1)
+    h = C.c_void_p()
+    assert lib.c0ip_batch_create(meshes, rhs, 1, None, None, C.byref(h)) == -6

@@ -248,3 +248,40 @@ def test_solve_not_converged_and_nan():
     with pytest.raises(P.C0ipError) as e:
         pb.solve(dev(bn), x)
     assert e.value.status == -5
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 32), (2, 3, 32), (2, 4, 16), (2, 5, 8), (2, 7, 8), (3, 2, 4), (3, 3, 4)])
+def test_smoother_step_out_of_place(dim, k, N):
+    """c0ip_smoother_step: x_out = S(x_in, b) (fused in 2D), x_in untouched."""
+    say("smoother_step", dim, k, N)
+    A, blocks, pidx = oracle_ops(dim, k, N)
+    x, b = vectors(dim, k, N)
+    om = 0.25 if dim == 2 else 0.1
+    pb = _problem(dim, k, N, omega=om)
+    xi = dev(x)
+    xo = torch.empty_like(xi)
+    pb.smoother_step(dev(b), xi, xo)
+    x0 = torch.empty_like(xi)
+    pb.smoother_step(dev(b), None, x0)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(xi), x)
+    assert rel_l2(host(xo), O.avs_apply(A, blocks, pidx, x, b, om, 1)) <= fp64_tol(dim, k, N)
+    assert rel_l2(host(x0), O.avs_apply(A, blocks, pidx, None, b, om, 1, x_is_zero=True)) <= fp64_tol(dim, k, N)
+    with pytest.raises(P.C0ipError):
+        pb.smoother_step(dev(b), xi, xi)
+
+
+@pytest.mark.parametrize("pre,post", [(2, 2), (1, 3), (0, 1), (3, 0)])
+def test_vcycle_smoothing_steps(pre, post):
+    """V-cycles with several (or no) pre/post steps: the fused out-of-place
+    steps alternate buffers; the result must land in x."""
+    dim, k, N = 2, 3, 32
+    say("vcycle steps", pre, post)
+    H = O.Hierarchy(dim, k, N, omega=0.25, pre=pre, post=post)
+    _, b = vectors(dim, k, N)
+    ref = H.vcycle(b)
+    pb = _problem(dim, k, N, omega=0.25, pre_steps=pre, post_steps=post, vcycle_dtype=P.C0IP_F64)
+    xd = torch.empty(b.size, dtype=torch.float64, device="cuda")
+    pb.vcycle(dev(b), xd)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xd), ref) <= 10 * fp64_tol(dim, k, N)
