@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--omega", type=float, default=0.25)
     ap.add_argument("--reps", type=int, default=30, help="kernel timing repetitions")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-N", type=int, default=64, help="cells per direction of the oracle sample")
+    ap.add_argument("--cpu-N", type=int, default=128, help="cells per direction of the oracle sample")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-problem workload")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D Q3 128^3 kernel rates")
     ap.add_argument("--only", default=None,
                     choices=["matvec_f64", "smoother_f64", "matvec_f32", "smoother_f32", "copy_f64"],
@@ -64,8 +65,9 @@ def only_kernel(args):
         x, b = x.float(), b.float()
     y = torch.zeros_like(x)
     pb = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F32)
+    pb.autotune()
     fn = {"matvec_f64": lambda: pb.apply_A(x, y), "matvec_f32": lambda: pb.apply_A(x, y),
-          "smoother_f64": lambda: pb.apply_smoother(b, y), "smoother_f32": lambda: pb.apply_smoother(b, y),
+          "smoother_f64": lambda: pb.smoother_step(b, x, y), "smoother_f32": lambda: pb.smoother_step(b, x, y),
           "copy_f64": lambda: y.copy_(x)}[args.only]
     ms = time_kernel(lambda _: fn(), [None], args.reps, torch)
     print(json.dumps({"only": args.only, "ms": ms, "dofs": n, "reps": args.reps}), flush=True)
@@ -126,11 +128,11 @@ def bench_3d(args, torch, P):
     sets = [(x, torch.zeros(n, dtype=torch.float64, device=dev), b) for _ in range(2)]
     reps = max(3, args.reps // 5)
     ms_mv = time_kernel(lambda s: pb.apply_A(s[0], s[1]), sets, reps, torch)
-    ms_sm = time_kernel(lambda s: pb.apply_smoother(s[2], s[1]), sets, reps, torch)
+    ms_sm = time_kernel(lambda s: pb.smoother_step(s[2], s[0], s[1]), sets, reps, torch)
     x32, b32 = x.float(), b.float()
     sets32 = [(x32, torch.zeros(n, dtype=torch.float32, device=dev), b32) for _ in range(2)]
     ms_mv32 = time_kernel(lambda s: pb.apply_A(s[0], s[1]), sets32, reps, torch)
-    ms_sm32 = time_kernel(lambda s: pb.apply_smoother(s[2], s[1]), sets32, reps, torch)
+    ms_sm32 = time_kernel(lambda s: pb.smoother_step(s[2], s[0], s[1]), sets32, reps, torch)
     del sets, sets32, x, b, x32, b32
     pb.close()
     torch.cuda.empty_cache()
@@ -139,6 +141,62 @@ def bench_3d(args, torch, P):
                           ("smoother_f32", ms_sm32, 12)]:
         out[name] = {"ms": ms, "dofs_per_s": n / (ms * 1e-3), "alg_GBs": byt * n / (ms * 1e-3) / 1e9}
     return out
+
+
+def c5_problems():
+    """Batched workload: 16 right-hand sides (seeds 0-15) on 2D Q4 256^2, plus
+    48 problems i = 0..47 with N_i = 2^(3 + i mod 5) cells per direction,
+    degree 2 + (i // 5) mod 3, right-hand side seed 1000 + i."""
+    probs = [(256, 4)]
+    rhs = [16]
+    seeds = [list(range(16))]
+    for i in range(48):
+        probs.append((2 ** (3 + i % 5), 2 + (i // 5) % 3))
+        rhs.append(1)
+        seeds.append([1000 + i])
+    return probs, rhs, seeds
+
+
+def bench_batch(torch, P):
+    """All 64 systems in one batch (one graph replay per round) vs the same
+    64 systems solved one after another; float32 V-cycle, FGMRES to 1e-8."""
+    from paper_2412_05082_amd.inputs import seeded_vector
+    probs, rhs, seeds = c5_problems()
+    dev = torch.device("cuda:0")
+    bs = [torch.from_numpy(__import__("numpy").stack([seeded_vector(2, k, N, sd) for sd in sd_list])).to(dev)
+          for (N, k), sd_list in zip(probs, seeds)]
+    total = sum(b.numel() for b in bs)
+    bt = P.Batch(probs, rhs, omega=0.25, vcycle_dtype=P.C0IP_F32)
+    xs = [torch.zeros_like(b) for b in bs]
+    bt.solve(bs, xs)  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = bt.solve(bs, xs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    singles = [P.Problem(2, N, k, omega=0.25, vcycle_dtype=P.C0IP_F32) for N, k in probs]
+    xq = torch.zeros_like(bs[0][0])
+    for pb, b in zip(singles, bs):  # warm-up
+        pb.solve(b[0].contiguous(), torch.zeros_like(b[0]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for pb, b in zip(singles, bs):
+        for q in range(b.shape[0]):
+            x1 = torch.zeros_like(b[q])
+            its.append(pb.solve(b[q], x1)["iterations"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    del xq
+    bt.close()
+    for pb in singles:
+        pb.close()
+    return {"workload": "16 RHS on 2D Q4 256^2 + 48 uneven 2D problems (8^2..128^2 cells, Q2..Q4); "
+                        "float32 V-cycle, FGMRES(50) to 1e-8", "systems": len(infos), "dofs": total,
+            "batched_seconds": t_batch, "sequential_seconds": t_seq, "speedup": t_seq / t_batch,
+            "batched_dofs_per_s": total / t_batch, "max_iterations": max(i["iterations"] for i in infos),
+            "all_converged": all(i["converged"] == 1 for i in infos),
+            "iterations_equal_sequential": [i["iterations"] for i in infos] == its}
 
 
 def main():
@@ -164,21 +222,22 @@ def main():
     b = torch.from_numpy(b_np).to(dev)
     pmix = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F32)
     p64 = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F64)
+    pmix.autotune()  # set-up: pick the fused smoother's tile size per level
+    p64.autotune()
 
     # --- per-kernel rates, cold HBM (rotating sets > 1 GB in total)
     nsets = max(4, int(1.2e9 // (3 * 8 * n)) + 1)
     sets64 = [(torch.from_numpy(x_np).to(dev), torch.empty(n, dtype=torch.float64, device=dev), b)
               for _ in range(nsets)]
     ms_mv = time_kernel(lambda s: pmix.apply_A(s[0], s[1]), sets64, args.reps, torch)
-    sm_sets = [(s[2], s[1]) for s in sets64]
-    ms_sm0 = time_kernel(lambda s: pmix.apply_smoother(s[0], s[1], x_is_zero=True), sm_sets, args.reps, torch)
-    ms_smx = time_kernel(lambda s: pmix.apply_smoother(s[0], s[1]), sm_sets, args.reps, torch)
-    del sets64, sm_sets
+    ms_sm0 = time_kernel(lambda s: pmix.smoother_step(s[2], None, s[1]), sets64, args.reps, torch)
+    ms_smx = time_kernel(lambda s: pmix.smoother_step(s[2], s[0], s[1]), sets64, args.reps, torch)
+    del sets64
     b32 = b.float()
     sets32 = [(torch.from_numpy(x_np).float().to(dev), torch.zeros(n, dtype=torch.float32, device=dev), b32)
               for _ in range(nsets)]
     ms_mv32 = time_kernel(lambda s: pmix.apply_A(s[0], s[1]), sets32, args.reps, torch)
-    ms_smx32 = time_kernel(lambda s: pmix.apply_smoother(s[2], s[1]), sets32, args.reps, torch)
+    ms_smx32 = time_kernel(lambda s: pmix.smoother_step(s[2], s[0], s[1]), sets32, args.reps, torch)
     del sets32
     torch.cuda.empty_cache()
 
@@ -205,8 +264,8 @@ def main():
     ms_step = 1e3 * tsteps / args.steps
     value = n * args.steps / tsteps
 
-    # dominant kernel of the float32 V-cycle: the smoother with residual
-    bytes_sm32 = 12.0 * n  # read x, read b, write x (float32)
+    # dominant kernel of the float32 V-cycle: the fused smoother step S(x, b)
+    bytes_sm32 = 12.0 * n  # read x, read b, write x_out (float32)
     achieved = bytes_sm32 / (ms_smx32 * 1e-3) / 1e9
     out = {
         "metric": "DoFs/s of C0IP mat-vec and patch smoother; FP32-vs-FP64 MG-GMRES solve time",
@@ -243,10 +302,15 @@ def main():
             "smoother_f32": {"ms": ms_smx32, "dofs_per_s": n / (ms_smx32 * 1e-3),
                              "alg_GBs": 12.0 * n / (ms_smx32 * 1e-3) / 1e9},
         },
+        "tuned_tile_variant": {"f32": pmix.tuned_variant(dtype=P.C0IP_F32),
+                               "f64": p64.tuned_variant(dtype=P.C0IP_F64)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "float32 smoother step S(x,b) (residual + patch solve), 12 B/DoF"},
+                     "kernel": "avs2d_kernel<float,3,8>: fused float32 smoother step S(x,b) "
+                               "(residual in LDS + patch solves), 12 B/DoF x 2,362,369 DoFs per launch"},
     }
+    if not args.no_batch:
+        out["config_batched"] = bench_batch(torch, P)
     if not args.no_3d:
         del pmix, p64
         torch.cuda.empty_cache()

@@ -134,6 +134,17 @@ c0ip_status c0ip_apply_smoother(c0ip_problem* p, int level, c0ip_dtype dtype, co
 c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b, const void* x_in,
                                void* x_out);
 
+/* Autotuner: for every level (and each precision the handle has set up),
+ * time each compiled tile-size variant of the 2D fused smoother kernel
+ * (reps launches after one warm-up, on the handle's stream and work space)
+ * and keep the fastest for all later smoother steps of that level.
+ * Synchronises the stream; no-op in 3D.  reps < 1 selects 3. */
+c0ip_status c0ip_autotune(c0ip_problem* p, int reps);
+/* The tile variant the autotuner chose for a level (0 = default), and a
+ * manual override (EINVAL for a variant this degree was not compiled for). */
+c0ip_status c0ip_tuned_variant(const c0ip_problem* p, int level, c0ip_dtype dtype, int* variant);
+c0ip_status c0ip_set_variant(c0ip_problem* p, int level, c0ip_dtype dtype, int variant);
+
 /* x = MG_L(0, b): one V-cycle of Algorithm 1 on the finest level in the
  * given precision (coarse solve in float64), with the options' pre/post
  * steps and damping. */

@@ -63,6 +63,9 @@ _SIGS = {
     "c0ip_apply_smoother": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "c0ip_vcycle": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "c0ip_smoother_step": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "c0ip_autotune": (C.c_int, [C.c_void_p, C.c_int]),
+    "c0ip_tuned_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int)]),
+    "c0ip_set_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "c0ip_solve": (C.c_int, [C.c_void_p, C.POINTER(KrylovOpts), C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]),
     "c0ip_last_error": (C.c_char_p, []),
     "c0ip_batch_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_int), C.c_int, C.POINTER(MgOpts), C.c_void_p,
@@ -136,6 +139,18 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, reps=3):
+        """Time the smoother's tile variants per level and keep the fastest."""
+        _check(load_library().c0ip_autotune(self._h, reps))
+
+    def tuned_variant(self, level=-1, dtype=C0IP_F32):
+        v = C.c_int()
+        _check(load_library().c0ip_tuned_variant(self._h, level, dtype, C.byref(v)))
+        return v.value
+
+    def set_variant(self, variant, level=-1, dtype=C0IP_F32):
+        _check(load_library().c0ip_set_variant(self._h, level, dtype, variant))
 
     def num_levels(self) -> int:
         v = C.c_int()

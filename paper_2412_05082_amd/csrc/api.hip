@@ -69,6 +69,7 @@ struct LevelWork {
   DevBuf<T> x, b, r, scratch;   // V-cycle vectors and transfer scratch
   c0ip::LevelCoef<T> coef;
   c0ip::LevelEig<T> eig;
+  int avs_variant = 0;  // tile variant of the fused smoother (set by c0ip_autotune)
   bool ready = false;
 };
 
@@ -185,7 +186,8 @@ void c0ip_problem::smooth_from(int l, const T* b, T* from, T* x, int steps) {
     T* cur = from;
     T* oth = (from == x) ? w.r.p : x;
     for (int s = 0; s < steps; ++s) {
-      check(c0ip::launch_avs2d<T>(k, Nl, w.coef, w.eig, cur, b, oth, om, stream), "fused smoother");
+      check(c0ip::launch_avs2d<T>(k, Nl, w.coef, w.eig, cur, b, oth, om, stream, 1, 0, nullptr, w.avs_variant),
+            "fused smoother");
       std::swap(cur, oth);
     }
     if (cur != x)
@@ -269,6 +271,12 @@ template const c0ip::LevelCoef<double>& c0ip_internal_coef<double>(c0ip_problem*
 template const c0ip::LevelCoef<float>& c0ip_internal_coef<float>(c0ip_problem*, int);
 template const c0ip::LevelEig<double>& c0ip_internal_eig<double>(c0ip_problem*, int);
 template const c0ip::LevelEig<float>& c0ip_internal_eig<float>(c0ip_problem*, int);
+template <typename T>
+int c0ip_internal_variant(c0ip_problem* p, int level) {
+  return p->work<T>(level).avs_variant;
+}
+template int c0ip_internal_variant<double>(c0ip_problem*, int);
+template int c0ip_internal_variant<float>(c0ip_problem*, int);
 template const double* c0ip_internal_ptab<double>(c0ip_problem*, int);
 template const float* c0ip_internal_ptab<float>(c0ip_problem*, int);
 
@@ -455,7 +463,9 @@ c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, con
       if (!xi) {
         p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, bb, nullptr, xo, om, p->stream), "smoother");
       } else if (p->dim == 2) {
-        p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, xi, bb, xo, om, p->stream), "fused smoother");
+        p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, xi, bb, xo, om, p->stream, 1, 0, nullptr,
+                                       w.avs_variant),
+                 "fused smoother");
       } else {
         p->check(c0ip::launch_apply<T, T>(p->dim, p->k, Nl, w.coef, xi, bb, w.r.p, p->stream), "residual");
         p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, w.r.p, xi, xo, om, p->stream), "smoother");
@@ -467,6 +477,75 @@ c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, con
   } catch (const HipFail& h) {
     return hip_fail(h);
   }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_autotune(c0ip_problem* p, int reps) {
+  g_err.clear();
+  if (!p) return fail(C0IP_EINVAL, "NULL argument");
+  if (reps < 1) reps = 3;
+  if (p->dim != 2) return C0IP_OK;  // 3D kernels have one tile shape
+  try {
+    hipEvent_t e0, e1;
+    p->check(hipEventCreate(&e0), "event");
+    p->check(hipEventCreate(&e1), "event");
+    auto tune = [&](auto tag) {
+      using T = decltype(tag);
+      for (int l = 1; l <= p->L; ++l) {
+        LevelWork<T>& w = p->work<T>(l);
+        if (!w.ready) continue;
+        const int64_t n = p->lv[l]->ntot;
+        const int Nl = p->lv[l]->N;
+        p->check(c0ip::launch_fill_t<T>(n, T(0), w.x.p, p->stream), "fill");
+        p->check(c0ip::launch_fill_t<T>(n, T(0), w.b.p, p->stream), "fill");
+        float best = 1e30f;
+        int bestv = 0;
+        for (int v = 0; v < c0ip::avs2d_variants(p->k); ++v) {
+          p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, w.x.p, w.b.p, w.r.p, T(0.25), p->stream, 1, 0,
+                                         nullptr, v),
+                   "autotune");
+          p->check(hipEventRecord(e0, p->stream), "event");
+          for (int r = 0; r < reps; ++r)
+            p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, w.x.p, w.b.p, w.r.p, T(0.25), p->stream, 1, 0,
+                                           nullptr, v),
+                     "autotune");
+          p->check(hipEventRecord(e1, p->stream), "event");
+          p->check(hipEventSynchronize(e1), "sync");
+          float ms = 0;
+          p->check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+          if (ms < best) {
+            best = ms;
+            bestv = v;
+          }
+        }
+        w.avs_variant = bestv;
+      }
+    };
+    tune(double{});
+    tune(float{});
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  } catch (const HipFail& h) {
+    return hip_fail(h);
+  }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_set_variant(c0ip_problem* p, int level, c0ip_dtype dtype, int variant) {
+  if (!p) return fail(C0IP_EINVAL, "NULL argument");
+  if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
+  if (variant < 0 || variant >= c0ip::avs2d_variants(p->k)) return fail(C0IP_EINVAL, "no such variant");
+  const int l = resolve_level(p, level);
+  if (dtype == C0IP_F32) p->lv[l]->w32.avs_variant = variant;
+  else p->lv[l]->w64.avs_variant = variant;
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_tuned_variant(const c0ip_problem* p, int level, c0ip_dtype dtype, int* variant) {
+  if (!p || !variant) return fail(C0IP_EINVAL, "NULL argument");
+  if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
+  const int l = resolve_level(p, level);
+  *variant = dtype == C0IP_F32 ? p->lv[l]->w32.avs_variant : p->lv[l]->w64.avs_variant;
   return C0IP_OK;
 }
 

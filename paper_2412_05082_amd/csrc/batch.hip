@@ -362,7 +362,8 @@ void c0ip_batch::vcycle(Group& g) {
       hchk(launch_patch2d<T>(k, Nl, eig, b, nullptr, x, om, s, nA, nl, mask), "patch");
       T *cur = x, *oth = r;
       for (int st = 1; st < pre; ++st) {
-        hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, oth, om, s, nA, nl, mask), "fused smoother");
+        hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, oth, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
+           "fused smoother");
         std::swap(cur, oth);
       }
       if (cur != x) hchk(hipMemcpyAsync(x, cur, sizeof(T) * nA * nl, hipMemcpyDeviceToDevice, s), "copy");
@@ -398,7 +399,8 @@ void c0ip_batch::vcycle(Group& g) {
          "prolong");
     T* oth = post > 0 ? x : r;
     for (int st = 0; st < post; ++st) {
-      hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, oth, om, s, nA, nl, mask), "fused smoother");
+      hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, oth, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
+           "fused smoother");
       std::swap(cur, oth);
     }
     if (cur != x) hchk(hipMemcpyAsync(x, cur, sizeof(T) * nA * nl, hipMemcpyDeviceToDevice, s), "copy");
@@ -550,6 +552,8 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
       c0ip_mesh_desc md{2, 2 << g.Lmax, g.k, g.gamma};
       c0ip_mg_opts mo = mg;
       c0ip_status st = c0ip_create(&md, &mo, (void*)bt->s, &g.proto);
+      if (st != C0IP_OK) return st;
+      st = c0ip_autotune(g.proto, 3);
       if (st != C0IP_OK) return st;
       const bool f32 = mg.vcycle_dtype == C0IP_F32;
       for (int l = 0; l <= g.Lmax; ++l) {

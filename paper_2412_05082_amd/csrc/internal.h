@@ -14,4 +14,6 @@ const c0ip::LevelEig<T>& c0ip_internal_eig(c0ip_problem* p, int level);
 template <typename T>
 const T* c0ip_internal_ptab(c0ip_problem* p, int level);
 const double* c0ip_internal_coarse(c0ip_problem* p);
+template <typename T>
+int c0ip_internal_variant(c0ip_problem* p, int level);
 void c0ip_internal_set_error(const std::string& msg);

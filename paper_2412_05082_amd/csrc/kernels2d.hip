@@ -33,6 +33,19 @@ __device__ __forceinline__ int row_class(int g, int n1, int k, int left, int rig
   return 2 * left + g % k;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Remap the (x, y) tile index so that XCD c walks one contiguous band
+// of tiles (row-major): neighbouring tiles, whose halos overlap, then share
+// that XCD's L2.  A bijection for any grid size.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+  const int gx = gridDim.x, T = gx * gridDim.y;
+  const int L = blockIdx.x + blockIdx.y * gx;
+  const int c = L & 7, q = L >> 3;
+  const int logical = c * (T >> 3) + min(c, T & 7) + q;
+  bx = logical % gx;
+  by = logical / gx;
+}
+
 // Structural band of a row at position p in its cell (p = 0: vertex node).
 // M and L: support of one (p > 0) or two (p = 0) cells; B: one more cell
 // on each side through the point terms.
@@ -140,12 +153,14 @@ __global__ __launch_bounds__(kThreads) void apply2d_kernel(const Tin* __restrict
   x += blockIdx.z * zs;
   y += blockIdx.z * zs;
   if (RES) b += blockIdx.z * zs;
+  int tbx, tby;
+  xcd_tile(tbx, tby);
   __shared__ T sX[RY * RX];
   __shared__ T sU[RY * TX];
   __shared__ T sV[(TY + 2 * K) * TX];
   __shared__ T sW[(TY + 2 * K) * TX];
   __shared__ T sTab[tab_max<K>()];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int x0 = tbx * TX, y0 = tby * TY;
   const bool xin = periodic && x0 >= left && x0 + TX <= right0;
   const bool yin = periodic && y0 >= left && y0 + TY <= right0;
   {
@@ -225,7 +240,9 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
   __shared__ T sB[NP * NP * NN];
   __shared__ T sQ[4 * NN];
   __shared__ T sLam[4 * n];
-  const int cx0 = blockIdx.x * TC, cy0 = blockIdx.y * TC;
+  int tbx, tby;
+  xcd_tile(tbx, tby);
+  const int cx0 = tbx * TC, cy0 = tby * TC;
   const int ox = (cx0 - 1) * K + 1, oy = (cy0 - 1) * K + 1;  // global node of region (0,0)
   {
     T v[NL];
@@ -487,7 +504,9 @@ __global__ __launch_bounds__(kThreads) void avs2d_kernel(const T* __restrict__ x
   x += blockIdx.z * zs;
   b += blockIdx.z * zs;
   xout += blockIdx.z * zs;
-  const int cx0 = blockIdx.x * TC, cy0 = blockIdx.y * TC;
+  int tbx, tby;
+  xcd_tile(tbx, tby);
+  const int cx0 = tbx * TC, cy0 = tby * TC;
   const int x0 = (cx0 - 1) * K, y0 = (cy0 - 1) * K;  // residual tile origin (a vertex node)
   T* sX = pool;
   T* sU = sX + RY * RX;
@@ -563,24 +582,36 @@ __global__ __launch_bounds__(kThreads) void avs2d_kernel(const T* __restrict__ x
   }
 }
 
-template <int K> struct FusedTile2D;
-template <> struct FusedTile2D<2> { static constexpr int TC = 16; };
-template <> struct FusedTile2D<3> { static constexpr int TC = 8; };
-template <> struct FusedTile2D<4> { static constexpr int TC = 8; };
-template <> struct FusedTile2D<5> { static constexpr int TC = 4; };
-template <> struct FusedTile2D<6> { static constexpr int TC = 4; };
-template <> struct FusedTile2D<7> { static constexpr int TC = 4; };
+// Tile sizes (owned cells per side) the fused smoother is compiled for;
+// variant 0 is the default, the autotuner may pick any of them per level.
+template <int K> struct FusedTiles;
+template <> struct FusedTiles<2> { static constexpr int n = 3, tc[3] = {16, 8, 24}; };
+template <> struct FusedTiles<3> { static constexpr int n = 3, tc[3] = {8, 4, 12}; };
+template <> struct FusedTiles<4> { static constexpr int n = 2, tc[3] = {8, 4, 8}; };
+template <> struct FusedTiles<5> { static constexpr int n = 2, tc[3] = {4, 2, 4}; };
+template <> struct FusedTiles<6> { static constexpr int n = 2, tc[3] = {4, 2, 4}; };
+template <> struct FusedTiles<7> { static constexpr int n = 2, tc[3] = {4, 2, 4}; };
 
-template <typename T, int K>
-hipError_t avs2d_k(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout, T omega,
-                   hipStream_t s, int nsys, int64_t zs, const int* active) {
-  constexpr int TC = FusedTile2D<K>::TC;
+template <typename T, int K, int TC>
+hipError_t avs2d_tc(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout, T omega,
+                    hipStream_t s, int nsys, int64_t zs, const int* active) {
   const int n1 = K * N + 1;
   const int nt = (N + TC - 1) / TC;
   avs2d_kernel<T, K, TC><<<dim3(nt, nt, nsys), kThreads, 0, s>>>(x, b, xout, N, n1, c.tab, c.nclass, c.left,
                                                                  c.right0, c.periodic, e.Q, e.lam, omega, zs,
                                                                  active);
   return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t avs2d_k(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout, T omega,
+                   hipStream_t s, int nsys, int64_t zs, const int* active, int variant) {
+  using F = FusedTiles<K>;
+  switch (variant < F::n ? variant : 0) {
+    case 1: return avs2d_tc<T, K, F::tc[1]>(N, c, e, x, b, xout, omega, s, nsys, zs, active);
+    case 2: return avs2d_tc<T, K, F::tc[2]>(N, c, e, x, b, xout, omega, s, nsys, zs, active);
+    default: return avs2d_tc<T, K, F::tc[0]>(N, c, e, x, b, xout, omega, s, nsys, zs, active);
+  }
 }
 
 template <int K> struct PatchTile2D;
@@ -802,15 +833,26 @@ template hipError_t launch_prolong2d<float>(int, int, const float*, const float*
                                             int, int64_t, int64_t, const int*);
 template <typename T>
 hipError_t launch_avs2d(int k, int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout,
-                        T omega, hipStream_t s, int nsys, int64_t zs, const int* active) {
-#define CALL(K) avs2d_k<T, K>(N, c, e, x, b, xout, omega, s, nsys, zs, active)
+                        T omega, hipStream_t s, int nsys, int64_t zs, const int* active, int variant) {
+#define CALL(K) avs2d_k<T, K>(N, c, e, x, b, xout, omega, s, nsys, zs, active, variant)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
+int avs2d_variants(int k) {
+  switch (k) {
+    case 2: return FusedTiles<2>::n;
+    case 3: return FusedTiles<3>::n;
+    case 4: return FusedTiles<4>::n;
+    case 5: return FusedTiles<5>::n;
+    case 6: return FusedTiles<6>::n;
+    case 7: return FusedTiles<7>::n;
+    default: return 1;
+  }
+}
 template hipError_t launch_avs2d<double>(int, int, const LevelCoef<double>&, const LevelEig<double>&, const double*,
-                                         const double*, double*, double, hipStream_t, int, int64_t, const int*);
+                                         const double*, double*, double, hipStream_t, int, int64_t, const int*, int);
 template hipError_t launch_avs2d<float>(int, int, const LevelCoef<float>&, const LevelEig<float>&, const float*,
-                                        const float*, float*, float, hipStream_t, int, int64_t, const int*);
+                                        const float*, float*, float, hipStream_t, int, int64_t, const int*, int);
 template hipError_t launch_apply2d<double, double>(int, int, const LevelCoef<double>&, const double*,
                                                    const double*, double*, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_apply2d<float, double>(int, int, const LevelCoef<double>&, const float*,

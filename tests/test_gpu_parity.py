@@ -285,3 +285,33 @@ def test_vcycle_smoothing_steps(pre, post):
     pb.vcycle(dev(b), xd)
     torch.cuda.synchronize()
     assert rel_l2(host(xd), ref) <= 10 * fp64_tol(dim, k, N)
+
+
+@pytest.mark.parametrize("k,N", [(2, 64), (3, 32), (4, 16), (5, 8), (7, 8)])
+def test_every_fused_tile_variant_and_autotune(k, N):
+    """Each compiled tile size of the fused smoother gives the oracle's
+    S(x, b); the autotuner picks one of them."""
+    dim = 2
+    say("fused variants", k, N)
+    A, blocks, pidx = oracle_ops(dim, k, N)
+    x, b = vectors(dim, k, N)
+    ref = O.avs_apply(A, blocks, pidx, x, b, 0.25, 1)
+    pb = _problem(dim, k, N, omega=0.25)
+    nvar = 0
+    for v in range(3):
+        try:
+            pb.set_variant(v, dtype=P.C0IP_F64)
+        except P.C0ipError:
+            break
+        nvar += 1
+        xo = torch.empty(x.size, dtype=torch.float64, device="cuda")
+        pb.smoother_step(dev(b), dev(x), xo)
+        torch.cuda.synchronize()
+        assert rel_l2(host(xo), ref) <= fp64_tol(dim, k, N), v
+    assert nvar >= 2
+    pb.autotune()
+    assert 0 <= pb.tuned_variant(dtype=P.C0IP_F64) < nvar
+    xo = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    pb.smoother_step(dev(b), dev(x), xo)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xo), ref) <= fp64_tol(dim, k, N)
