@@ -19,6 +19,8 @@
 // Owner-computes: a workgroup owns a tile of TC x TC cells, solves the
 // (TC+1)^2 patches that touch it (neighbouring tiles solve shared patches
 // twice instead of racing on writes), and writes each owned DoF once.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace c0ip {
@@ -141,11 +143,27 @@ __device__ __forceinline__ void y_sweeps(const T* __restrict__ sU, const T* __re
 // periodic ones, or one per row on levels with kN+1 <= 5k+2 nodes).
 template <int K> __host__ __device__ constexpr int tab_max() { return 3 * (5 * K + 2) * (4 * K + 1); }
 
+// Persistent form: a workgroup walks several tiles of its XCD's band (see
+// xcd_tile); the global loads of the next tile are issued into registers
+// before the current tile's sweeps, so their latency overlaps compute.
+// XCD c owns tiles [start_c, start_c + len_c) (row-major over the tile grid);
+// its g_c workgroups take every g_c-th tile of that band.
+__device__ __forceinline__ void band_of_block(int ntiles, int& t0, int& tend, int& stride) {
+  const int G = gridDim.x, bi = blockIdx.x, c = bi & 7, i = bi >> 3;
+  const int g = (G - c + 7) >> 3;
+  const int len = (ntiles >> 3) + (c < (ntiles & 7) ? 1 : 0);
+  const int start = c * (ntiles >> 3) + min(c, ntiles & 7);
+  t0 = start + i;
+  tend = start + len;
+  stride = g;
+}
+
 template <typename Tin, typename T, int K, int TXC, int TYC, bool RES>
 __global__ __launch_bounds__(kThreads) void apply2d_kernel(const Tin* __restrict__ x, const T* __restrict__ b,
-                                                           T* __restrict__ y, int n1, const T* __restrict__ tab,
-                                                           int nclass, int left, int right0, int periodic,
-                                                           int64_t zs, const int* __restrict__ active) {
+                                                           T* __restrict__ y, int n1, int tiles_x, int ntiles,
+                                                           const T* __restrict__ tab, int nclass, int left,
+                                                           int right0, int periodic, int64_t zs,
+                                                           const int* __restrict__ active) {
   constexpr int H = 2 * K, TX = TXC * K, TY = TYC * K, RX = TX + 2 * H, RY = TY + 2 * H;
   constexpr int NL = (RY * RX + kThreads - 1) / kThreads;
   if (active && !active[blockIdx.z]) return;
@@ -153,48 +171,75 @@ __global__ __launch_bounds__(kThreads) void apply2d_kernel(const Tin* __restrict
   x += blockIdx.z * zs;
   y += blockIdx.z * zs;
   if (RES) b += blockIdx.z * zs;
-  int tbx, tby;
-  xcd_tile(tbx, tby);
   __shared__ T sX[RY * RX];
   __shared__ T sU[RY * TX];
   __shared__ T sV[(TY + 2 * K) * TX];
   __shared__ T sW[(TY + 2 * K) * TX];
   __shared__ T sTab[tab_max<K>()];
-  const int x0 = tbx * TX, y0 = tby * TY;
-  const bool xin = periodic && x0 >= left && x0 + TX <= right0;
-  const bool yin = periodic && y0 >= left && y0 + TY <= right0;
   {
-    // all global loads of the tile are issued before the first LDS store
-    T v[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = threadIdx.x + q * kThreads;
-      const int r = e / RX, c = e - r * RX;
-      const int gy = y0 - H + r, gx = x0 - H + c;
-      v[q] = (e < RY * RX && gy >= 0 && gy < n1 && gx >= 0 && gx < n1) ? (T)x[(size_t)gy * n1 + gx] : T(0);
-    }
-    if (!(xin && yin)) {
-      const int ntab = 3 * nclass * (4 * K + 1);
-      for (int e = threadIdx.x; e < ntab; e += kThreads) sTab[e] = tab[e];
-    }
+    const int ntab = 3 * nclass * (4 * K + 1);
+    for (int e = threadIdx.x; e < ntab; e += kThreads) sTab[e] = tab[e];
+  }
+  int t, tend, stride;
+  band_of_block(ntiles, t, tend, stride);
+  T v[NL];
+#define C0IP_LOAD_TILE(tt)                                                                              \
+  {                                                                                                     \
+    const int lx0 = ((tt) % tiles_x) * TX, ly0 = ((tt) / tiles_x) * TY;                                 \
+    _Pragma("unroll") for (int q = 0; q < NL; ++q) {                                                    \
+      const int e = threadIdx.x + q * kThreads;                                                         \
+      const int r = e / RX, c = e - r * RX;                                                             \
+      const int gy = ly0 - H + r, gx = lx0 - H + c;                                                     \
+      v[q] = (e < RY * RX && gy >= 0 && gy < n1 && gx >= 0 && gx < n1) ? (T)x[(size_t)gy * n1 + gx]     \
+                                                                        : T(0);                         \
+    }                                                                                                   \
+  }
+  if (t < tend) C0IP_LOAD_TILE(t)
+  for (; t < tend; t += stride) {
+    const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
+    __syncthreads();  // the previous tile is done with sX, sU, sV, sW
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       const int e = threadIdx.x + q * kThreads;
       if (e < RY * RX) sX[e] = v[q];
     }
+    __syncthreads();
+    if (t + stride < tend) C0IP_LOAD_TILE(t + stride)  // in flight during the sweeps below
+    const bool xin = periodic && x0 >= left && x0 + TX <= right0;
+    const bool yin = periodic && y0 >= left && y0 + TY <= right0;
+    // interior tiles: wave-uniform coefficient addresses in the global table
+    // (scalar loads); boundary tiles: per-lane class rows from the LDS copy
+    if (xin)
+      x_sweeps<T, K, TXC, TYC, true>(sX, sU, sV, sW, x0, n1, tab, nclass, left, right0, periodic);
+    else
+      x_sweeps<T, K, TXC, TYC, false>(sX, sU, sV, sW, x0, n1, sTab, nclass, left, right0, periodic);
+    __syncthreads();
+    if (yin)
+      y_sweeps<T, K, TXC, TYC, true, RES>(sU, sV, sW, x0, y0, n1, tab, nclass, left, right0, periodic, b, y);
+    else
+      y_sweeps<T, K, TXC, TYC, false, RES>(sU, sV, sW, x0, y0, n1, sTab, nclass, left, right0, periodic, b, y);
   }
-  __syncthreads();
-  // interior tiles: wave-uniform coefficient addresses in the global table
-  // (scalar loads); boundary tiles: per-lane class rows from the LDS copy
-  if (xin)
-    x_sweeps<T, K, TXC, TYC, true>(sX, sU, sV, sW, x0, n1, tab, nclass, left, right0, periodic);
-  else
-    x_sweeps<T, K, TXC, TYC, false>(sX, sU, sV, sW, x0, n1, sTab, nclass, left, right0, periodic);
-  __syncthreads();
-  if (yin)
-    y_sweeps<T, K, TXC, TYC, true, RES>(sU, sV, sW, x0, y0, n1, tab, nclass, left, right0, periodic, b, y);
-  else
-    y_sweeps<T, K, TXC, TYC, false, RES>(sU, sV, sW, x0, y0, n1, sTab, nclass, left, right0, periodic, b, y);
+#undef C0IP_LOAD_TILE
+}
+
+// Resident workgroups of a kernel on the whole device (cached per kernel).
+template <typename KernelT>
+int device_slots(KernelT kernel) {
+  static int slots = 0;
+  if (slots == 0) {
+    int dev = 0, ncu = 0, occ = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kThreads, 0);
+    slots = std::max(8, ncu * std::max(occ, 1));
+  }
+  return slots;
+}
+
+inline int persistent_grid(int ntiles, int slots) {
+  if (ntiles <= 8) return ntiles;
+  int g = std::min(ntiles, slots);
+  return g >= 8 ? (g & ~7) : g;
 }
 
 template <int K> struct ApplyTile2D;
@@ -210,13 +255,19 @@ hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* 
                      int64_t zs, const int* active) {
   constexpr int TXC = ApplyTile2D<K>::TXC, TYC = ApplyTile2D<K>::TYC;
   const int n1 = K * N + 1;
-  dim3 grid((n1 + TXC * K - 1) / (TXC * K), (n1 + TYC * K - 1) / (TYC * K), nsys);
-  if (b)
-    apply2d_kernel<Tin, T, K, TXC, TYC, true><<<grid, kThreads, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left,
-                                                                        c.right0, c.periodic, zs, active);
-  else
-    apply2d_kernel<Tin, T, K, TXC, TYC, false><<<grid, kThreads, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left,
-                                                                         c.right0, c.periodic, zs, active);
+  const int tx = (n1 + TXC * K - 1) / (TXC * K), ty = (n1 + TYC * K - 1) / (TYC * K);
+  const int nt = tx * ty;
+  if (b) {
+    auto kern = apply2d_kernel<Tin, T, K, TXC, TYC, true>;
+    const int G = persistent_grid(nt, device_slots(kern));
+    kern<<<dim3(G, 1, nsys), kThreads, 0, s>>>(x, b, y, n1, tx, nt, c.tab, c.nclass, c.left, c.right0, c.periodic,
+                                               zs, active);
+  } else {
+    auto kern = apply2d_kernel<Tin, T, K, TXC, TYC, false>;
+    const int G = persistent_grid(nt, device_slots(kern));
+    kern<<<dim3(G, 1, nsys), kThreads, 0, s>>>(x, b, y, n1, tx, nt, c.tab, c.nclass, c.left, c.right0, c.periodic,
+                                               zs, active);
+  }
   return hipGetLastError();
 }
 
