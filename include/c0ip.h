@@ -70,13 +70,19 @@ typedef struct {
  * coarse_mode: 0 = exact level-0 solve (float64 dense inverse from a
  *   Cholesky factorisation); 1 = one smoothing step with omega = 1.
  * scatter_mode: 0 = owner-computes tiles (deterministic, no atomics); other
- *   values are rejected with C0IP_EUNSUPPORTED. */
+ *   values are rejected with C0IP_EUNSUPPORTED.
+ * tail_levels: in 2D with degree <= 4, the lowest levels of the V-cycle can
+ *   run as one launch of a single workgroup per system, all their vectors
+ *   in LDS (same operations, fewer launches).  -1 = as many levels as fit
+ *   in LDS; 0 = none (every level on the tiled kernels); m > 0 = at most
+ *   levels 0..m-1.  Ignored in 3D and for degree > 4. */
 typedef struct {
   double omega;
   int pre_steps, post_steps;
   c0ip_dtype vcycle_dtype;
   int coarse_mode;
   int scatter_mode;
+  int tail_levels;
 } c0ip_mg_opts;
 
 /* Flexible GMRES options (Sec. 5.1: relative residual reduction 1e-8).
@@ -103,7 +109,7 @@ typedef struct {
 /* Create a problem: level hierarchy, 1D matrices, patch eigenbases, coarse
  * inverse, device tables and work space (Sec. 3-4).  opts may be NULL
  * (omega 1/4 in 2D and 0.1 in 3D, 1 pre- and 1 post-step, float32
- * V-cycle, exact coarse solve).  hip_stream is a hipStream_t or NULL.
+ * V-cycle, exact coarse solve, tail_levels -1).  hip_stream is a hipStream_t or NULL.
  * On success *out owns all device memory it allocated. */
 c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, void* hip_stream,
                         c0ip_problem** out);

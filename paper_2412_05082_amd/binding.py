@@ -28,7 +28,8 @@ class MeshDesc(C.Structure):
 
 class MgOpts(C.Structure):
     _fields_ = [("omega", C.c_double), ("pre_steps", C.c_int), ("post_steps", C.c_int),
-                ("vcycle_dtype", C.c_int), ("coarse_mode", C.c_int), ("scatter_mode", C.c_int)]
+                ("vcycle_dtype", C.c_int), ("coarse_mode", C.c_int), ("scatter_mode", C.c_int),
+                ("tail_levels", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -114,12 +115,12 @@ class Problem:
     """Owns a c0ip_problem handle (c0ip_create / c0ip_destroy)."""
 
     def __init__(self, dim, n_cells, degree, gamma=0.0, omega=None, pre_steps=1, post_steps=1,
-                 vcycle_dtype=C0IP_F32, coarse_mode=0, scatter_mode=0, stream=None):
+                 vcycle_dtype=C0IP_F32, coarse_mode=0, scatter_mode=0, tail_levels=-1, stream=None):
         lib = load_library()
         if omega is None:
             omega = 0.25 if dim == 2 else 0.1
         self.mesh = MeshDesc(dim, n_cells, degree, gamma)
-        self.mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode)
+        self.mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -206,13 +207,13 @@ class Batch:
     """Owns a c0ip_batch: problems = [(n_cells, degree), ...] (2D), n_rhs per problem."""
 
     def __init__(self, problems, n_rhs, gamma=0.0, omega=0.25, pre_steps=1, post_steps=1, vcycle_dtype=C0IP_F32,
-                 coarse_mode=0, stream=None):
+                 coarse_mode=0, tail_levels=-1, stream=None):
         lib = load_library()
         self.problems = list(problems)
         self.n_rhs = list(n_rhs)
         meshes = (MeshDesc * len(self.problems))(*[MeshDesc(2, N, k, gamma) for N, k in self.problems])
         rhs = (C.c_int * len(self.n_rhs))(*self.n_rhs)
-        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, 0)
+        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, 0, tail_levels)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

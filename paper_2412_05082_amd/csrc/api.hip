@@ -113,6 +113,14 @@ struct c0ip_problem {
   void smooth_from(int l, const T* b, T* from, T* x, int steps);
   template <typename T>
   void mg_level(int l, const T* b, T* x);
+  // top level of the single-workgroup tail V-cycle in precision T (-1: none)
+  int tailLT[2] = {-2, -2};
+  template <typename T>
+  int tail_level();
+  template <typename T>
+  void fill_tail(c0ip::TailParams<T>& P);
+  template <typename T>
+  void run_tail(const T* b, T* x);
   void check(hipError_t e, const char* what) {
     if (e != hipSuccess) throw HipFail{e, what};
   }
@@ -201,9 +209,72 @@ void c0ip_problem::smooth_from(int l, const T* b, T* from, T* x, int steps) {
   }
 }
 
+// The tail runs levels 0..LT in one launch: LT is the highest level (at
+// most the finest, at most tail_levels - 1) whose vectors and tables fit in
+// the LDS of one workgroup; below level 1 there is nothing to gain.
+template <typename T>
+int c0ip_problem::tail_level() {
+  int& t = tailLT[sizeof(T) == 4 ? 1 : 0];
+  if (t != -2) return t;
+  t = -1;
+  if (dim != 2 || k > 4 || mg.tail_levels == 0) return t;
+  const int lim = c0ip::tail_lds_limit();
+  int cap = std::min(L, c0ip::kTailMaxLevels - 1);
+  if (mg.tail_levels > 0) cap = std::min(cap, mg.tail_levels - 1);
+  int nclass[c0ip::kTailMaxLevels] = {};
+  for (int l = 0; l <= cap; ++l) {
+    nclass[l] = lv[l]->rc.nclass;
+    if (c0ip::tail_bytes(k, l, nclass, (int)sizeof(T)) > lim) break;
+    if (l >= 1) t = l;
+  }
+  if (t >= 1 && c0ip::configure_vtail<T>(k, c0ip::tail_bytes(k, t, nclass, (int)sizeof(T))) != hipSuccess) {
+    (void)hipGetLastError();
+    t = -1;
+  }
+  return t;
+}
+
+template <typename T>
+void c0ip_problem::fill_tail(c0ip::TailParams<T>& P) {
+  const int LT = tail_level<T>();
+  P.LT = LT;
+  for (int l = 0; l <= LT; ++l) {
+    prepare<T>(l);
+    const LevelWork<T>& w = work<T>(l);
+    P.nclass[l] = w.coef.nclass;
+    P.left[l] = w.coef.left;
+    P.right0[l] = w.coef.right0;
+    P.periodic[l] = w.coef.periodic;
+    P.tab[l] = w.coef.tab;
+    P.Q[l] = w.eig.Q;
+    P.lam[l] = w.eig.lam;
+  }
+  P.ptab = work<T>(LT).ptab.p;
+  P.Ainv = A0inv.p;
+  P.omega = (T)mg.omega;
+  P.pre = mg.pre_steps;
+  P.post = mg.post_steps;
+  P.coarse_mode = mg.coarse_mode;
+}
+
+template <typename T>
+void c0ip_problem::run_tail(const T* b, T* x) {
+  c0ip::TailParams<T> P;
+  fill_tail<T>(P);
+  c0ip::TailIO<T> io;
+  for (int l = 0; l <= P.LT; ++l) io.nA[l] = 1;
+  io.b[P.LT] = b;
+  io.x[P.LT] = x;
+  check(c0ip::launch_vtail<T>(k, P, io, 1, stream), "tail V-cycle");
+}
+
 // x = MG_l(0, b) (Algorithm 1, returning right after the coarse solve).
 template <typename T>
 void c0ip_problem::mg_level(int l, const T* b, T* x) {
+  if (l >= 1 && l == tail_level<T>()) {
+    run_tail<T>(b, x);
+    return;
+  }
   if (l == 0) {
     if (mg.coarse_mode == 0) {
       check(c0ip::launch_coarse<T>(dim, k, A0inv.p, b, x, stream), "coarse solve");
@@ -275,6 +346,14 @@ template <typename T>
 int c0ip_internal_variant(c0ip_problem* p, int level) {
   return p->work<T>(level).avs_variant;
 }
+template <typename T>
+int c0ip_internal_tail(c0ip_problem* p, c0ip::TailParams<T>* P) {
+  const int LT = p->tail_level<T>();
+  if (LT >= 1) p->fill_tail<T>(*P);
+  return LT;
+}
+template int c0ip_internal_tail<double>(c0ip_problem*, c0ip::TailParams<double>*);
+template int c0ip_internal_tail<float>(c0ip_problem*, c0ip::TailParams<float>*);
 template int c0ip_internal_variant<double>(c0ip_problem*, int);
 template int c0ip_internal_variant<float>(c0ip_problem*, int);
 template const double* c0ip_internal_ptab<double>(c0ip_problem*, int);
@@ -300,6 +379,7 @@ c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, vo
     mg.vcycle_dtype = C0IP_F32;
     mg.coarse_mode = 0;
     mg.scatter_mode = 0;
+    mg.tail_levels = -1;
   }
   if (!(mg.omega > 0) || !std::isfinite(mg.omega)) return fail(C0IP_EINVAL, "omega must be > 0");
   if (mg.pre_steps < 0 || mg.post_steps < 0 || mg.pre_steps > 16 || mg.post_steps > 16)
@@ -307,6 +387,7 @@ c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, vo
   if (mg.vcycle_dtype != C0IP_F64 && mg.vcycle_dtype != C0IP_F32) return fail(C0IP_EINVAL, "bad vcycle_dtype");
   if (mg.coarse_mode != 0 && mg.coarse_mode != 1) return fail(C0IP_EINVAL, "coarse_mode must be 0 or 1");
   if (mg.scatter_mode != 0) return fail(C0IP_EUNSUPPORTED, "only scatter_mode 0 (owner-computes) is built");
+  if (mg.tail_levels < -1) return fail(C0IP_EINVAL, "tail_levels must be >= -1");
   std::unique_ptr<c0ip_problem> p(new c0ip_problem());
   p->dim = mesh->dim;
   p->k = mesh->degree;

@@ -348,7 +348,11 @@ void c0ip_batch::vcycle(Group& g) {
   const T om = (T)mg.omega;
   auto n1 = [&](int l) { return (int64_t)(k * (2 << l) + 1) * (k * (2 << l) + 1); };
   const int* mask = g.mask.p;
-  for (int l = g.Lmax; l >= 1; --l) {
+  // levels 0..LT run as one single-workgroup launch per system (LT < 1: none)
+  TailParams<T> tp;
+  const int LT = c0ip_internal_tail<T>(g.proto, &tp);
+  const int lo = LT >= 1 ? LT : 0;
+  for (int l = g.Lmax; l > lo; --l) {
     const int nA = g.A[l];
     if (nA == 0) continue;
     const int Nl = 2 << l;
@@ -373,7 +377,17 @@ void c0ip_batch::vcycle(Group& g) {
                               n1(l - 1), mask),
          "restrict");
   }
-  {
+  if (LT >= 1) {
+    TailIO<T> io;
+    for (int l = 0; l <= LT; ++l) {
+      io.b[l] = lvbuf<T>(g, 1, l).p;
+      io.x[l] = lvbuf<T>(g, 0, l).p;
+      io.stride[l] = n1(l);
+      io.nA[l] = g.A[l];
+    }
+    io.active = mask;
+    hchk(launch_vtail<T>(k, tp, io, g.A[0], s), "tail V-cycle");
+  } else {
     const int nA = g.A[0];
     if (mg.coarse_mode == 0)
       hchk(launch_coarse<T>(2, k, c0ip_internal_coarse(g.proto), lvbuf<T>(g, 1, 0).p, lvbuf<T>(g, 0, 0).p, s, nA,
@@ -384,7 +398,7 @@ void c0ip_batch::vcycle(Group& g) {
                              lvbuf<T>(g, 0, 0).p, T(1), s, nA, n1(0), mask),
            "coarse smooth");
   }
-  for (int l = 1; l <= g.Lmax; ++l) {
+  for (int l = lo + 1; l <= g.Lmax; ++l) {
     const int nA = g.A[l];
     if (nA == 0) continue;
     const int Nl = 2 << l;
@@ -499,6 +513,7 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
     mg.vcycle_dtype = C0IP_F32;
     mg.coarse_mode = 0;
     mg.scatter_mode = 0;
+    mg.tail_levels = -1;
   }
   std::unique_ptr<c0ip_batch> bt(new c0ip_batch());
   bt->mg = mg;
@@ -556,6 +571,14 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
       st = c0ip_autotune(g.proto, 3);
       if (st != C0IP_OK) return st;
       const bool f32 = mg.vcycle_dtype == C0IP_F32;
+      {  // choose (and allow the LDS of) the tail before any graph capture
+        TailParams<float> t32;
+        TailParams<double> t64;
+        if (f32)
+          (void)c0ip_internal_tail<float>(g.proto, &t32);
+        else
+          (void)c0ip_internal_tail<double>(g.proto, &t64);
+      }
       for (int l = 0; l <= g.Lmax; ++l) {
         const int64_t nl = (int64_t)(g.k * (2 << l) + 1) * (g.k * (2 << l) + 1);
         const size_t cnt = (size_t)g.A[l] * nl;

@@ -16,4 +16,8 @@ const T* c0ip_internal_ptab(c0ip_problem* p, int level);
 const double* c0ip_internal_coarse(c0ip_problem* p);
 template <typename T>
 int c0ip_internal_variant(c0ip_problem* p, int level);
+// Parameters of the single-workgroup tail V-cycle (levels 0..LT) for this
+// problem's options; returns LT, or -1 when the tail is not used.
+template <typename T>
+int c0ip_internal_tail(c0ip_problem* p, c0ip::TailParams<T>* P);
 void c0ip_internal_set_error(const std::string& msg);

@@ -113,6 +113,43 @@ template <typename T>
 hipError_t launch_patch3d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
                           hipStream_t s);
 
+// Lowest levels 0..LT of the 2D V-cycle in one launch, one workgroup per
+// system, every vector in LDS (vtail.hip).  Tables as on the tiled path.
+constexpr int kTailMaxLevels = 5;
+template <typename T>
+struct TailParams {
+  int LT = 0;  // top level of the tail
+  int nclass[kTailMaxLevels] = {}, left[kTailMaxLevels] = {}, right0[kTailMaxLevels] = {},
+      periodic[kTailMaxLevels] = {};
+  const T* tab[kTailMaxLevels] = {};
+  const T* Q[kTailMaxLevels] = {};
+  const T* lam[kTailMaxLevels] = {};
+  const T* ptab = nullptr;       // embedding table [2][k][k+1]
+  const double* Ainv = nullptr;  // level-0 inverse (coarse_mode 0)
+  T omega = 0;
+  int pre = 1, post = 1, coarse_mode = 0;
+};
+// Per-level slot buffers: system s exists on level l iff s < nA[l]; its
+// vectors start at b[l] + s * stride[l] (x likewise).  A system's tail
+// starts at its highest level <= LT: b there is read, x there is written.
+template <typename T>
+struct TailIO {
+  const T* b[kTailMaxLevels] = {};
+  T* x[kTailMaxLevels] = {};
+  int64_t stride[kTailMaxLevels] = {};
+  int nA[kTailMaxLevels] = {};
+  const int* active = nullptr;
+};
+// LDS bytes of the tail kernel for degree k up to level LT (nclass per level).
+int tail_bytes(int k, int LT, const int* nclass, int elem_size);
+// Largest LDS a workgroup may use on the current device.
+int tail_lds_limit();
+// Allow the tail kernel of degree k `bytes` of dynamic LDS (before launch or capture).
+template <typename T>
+hipError_t configure_vtail(int k, int bytes);
+template <typename T>
+hipError_t launch_vtail(int k, const TailParams<T>& P, const TailIO<T>& io, int nsys, hipStream_t s);
+
 #define C0IP_DISPATCH_K(k, CALL)          \
   switch (k) {                            \
     case 2: return CALL(2);               \

@@ -21,10 +21,14 @@ def _rhs(N, k, r, seed0):
     return np.stack([seeded_vector(2, k, N, seed0 + q) for q in range(r)])
 
 
+@pytest.mark.parametrize("tail", [-1, 0])
 @pytest.mark.parametrize("dtype", [P.C0IP_F32, P.C0IP_F64])
-def test_batch_matches_single_solves(dtype):
-    say("batch vs single", dtype)
-    bt = P.Batch(PROBLEMS, NRHS, omega=0.25, vcycle_dtype=dtype)
+def test_batch_matches_single_solves(dtype, tail):
+    """tail -1: the lowest levels of every system run in the single-workgroup
+    tail launch (systems whose hierarchy is shorter start it at their own
+    finest level); tail 0: every level on the tiled kernels."""
+    say("batch vs single", dtype, tail)
+    bt = P.Batch(PROBLEMS, NRHS, omega=0.25, vcycle_dtype=dtype, tail_levels=tail)
     assert bt.num_systems() == sum(NRHS)
     bs = [torch.from_numpy(_rhs(N, k, r, 100 * i)).cuda() for i, ((N, k), r) in enumerate(zip(PROBLEMS, NRHS))]
     for rep in range(2):
@@ -33,7 +37,7 @@ def test_batch_matches_single_solves(dtype):
         torch.cuda.synchronize()
         t = 0
         for i, ((N, k), r) in enumerate(zip(PROBLEMS, NRHS)):
-            pb = P.Problem(2, N, k, omega=0.25, vcycle_dtype=dtype)
+            pb = P.Problem(2, N, k, omega=0.25, vcycle_dtype=dtype, tail_levels=tail)
             A = O.assemble(2, k, N) if N <= 32 else None
             for q in range(r):
                 b = bs[i][q].contiguous()
