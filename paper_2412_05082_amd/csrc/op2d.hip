@@ -232,20 +232,36 @@ template <typename Tin, typename T, class G, bool RES>
 __global__ __launch_bounds__(G::NTH) void apply2d_kernel(const Tin* __restrict__ x, const T* __restrict__ b,
                                                          T* __restrict__ y, int n1, const T* __restrict__ tab,
                                                          int nclass, int left, int right0, int periodic, int64_t zs,
-                                                         const int* __restrict__ active) {
+                                                         const int* __restrict__ active, tile::TileOrder ord) {
   if (active && !active[blockIdx.z]) return;
+  int bx, by;
+  if (!tile::tile_of_block(ord, blockIdx.x, bx, by)) return;
   x += blockIdx.z * zs;
   y += blockIdx.z * zs;
   if (RES) b += blockIdx.z * zs;
   __shared__ T sX[G::RY * G::RX];
   __shared__ T sT[G::RY * G::TX];
   __shared__ T sTab[G::TABMAX];
-  int bx, by;
-  tile::xcd_tile(bx, by);
   const int x0 = bx * G::TX, y0 = by * G::TY;
   stage_x<Tin, T, G>(x, sX, x0, y0, n1);
   stage_tab<T, G>(tab, sTab, nclass,
                   !(tile_xin<G>(periodic, left, right0, x0) && tile_yin<G>(periodic, left, right0, y0)));
+  // b of the outputs (residual form), loaded now to overlap the passes
+  T bv[RES ? G::NI : 1][G::RW * G::K];
+  if constexpr (RES) {
+#pragma unroll
+    for (int q = 0; q < G::NI; ++q) {
+      const int it = threadIdx.x + q * G::NTH;
+      const int cg = it / G::TX, l = it - cg * G::TX;
+      const int gx = x0 + l;
+#pragma unroll
+      for (int w = 0; w < G::RW * G::K; ++w) {
+        const int gy = y0 + cg * G::RW * G::K + w;
+        const bool inner = it < G::NIT_Y && gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2;
+        bv[q][w] = inner ? b[(size_t)gy * n1 + gx] : T(0);
+      }
+    }
+  }
   T acc[G::NI][G::RW * G::K];
   __syncthreads();
   op_tile_any<T, G>(sX, sT, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
@@ -260,9 +276,9 @@ __global__ __launch_bounds__(G::NTH) void apply2d_kernel(const Tin* __restrict__
       const int gy = y0 + cg * G::RW * G::K + w;
       if (gx < n1 && gy < n1) {
         const size_t idx = (size_t)gy * n1 + gx;
-        if (RES) {
+        if constexpr (RES) {
           const bool bnd = gx == 0 || gy == 0 || gx == n1 - 1 || gy == n1 - 1;
-          y[idx] = bnd ? T(0) : b[idx] - acc[q][w];
+          y[idx] = bnd ? T(0) : bv[q][w] - acc[q][w];
         } else {
           y[idx] = acc[q][w];
         }
@@ -286,13 +302,17 @@ hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* 
                      int64_t zs, const int* active) {
   using G = typename ApplyCfg<K>::G;
   const int n1 = K * N + 1;
-  const dim3 grid((n1 + G::TX - 1) / G::TX, (n1 + G::TY - 1) / G::TY, nsys);
+  const int tx = (n1 + G::TX - 1) / G::TX, ty = (n1 + G::TY - 1) / G::TY;
+  const tile::TileOrder ord = tile::make_order(
+      tx, ty, [&](int bx) { return c.periodic && bx * G::TX >= c.left && bx * G::TX + G::TX <= c.right0; },
+      [&](int by) { return c.periodic && by * G::TY >= c.left && by * G::TY + G::TY <= c.right0; });
+  const dim3 grid(tile::order_blocks(ord), 1, nsys);
   if (b)
     apply2d_kernel<Tin, T, G, true><<<grid, G::NTH, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left, c.right0,
-                                                            c.periodic, zs, active);
+                                                            c.periodic, zs, active, ord);
   else
     apply2d_kernel<Tin, T, G, false><<<grid, G::NTH, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left, c.right0,
-                                                             c.periodic, zs, active);
+                                                             c.periodic, zs, active, ord);
   return hipGetLastError();
 }
 
@@ -363,7 +383,8 @@ __device__ __forceinline__ void patch_solves(const T* __restrict__ sRr, T* __res
       T s = 0;
 #pragma unroll
       for (int a = 0; a < n; ++a) s += q[a * n + ap] * col[a];
-      t[ap] = INTERIOR ? s * sD[ap * n + c] : s / (sLam[tx * n + c] + sLam[ty * n + ap]);
+      // the same rounding on every path: s times the rounded reciprocal
+      t[ap] = s * (INTERIOR ? sD[ap * n + c] : T(1) / (sLam[tx * n + c] + sLam[ty * n + ap]));
     }
 #pragma unroll
     for (int a = 0; a < n; ++a) {
@@ -400,7 +421,8 @@ __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, 
                                                        T* __restrict__ xout, int N, int n1, const T* __restrict__ tab,
                                                        int nclass, int left, int right0, int periodic,
                                                        const T* __restrict__ Qg, const T* __restrict__ lamg, T omega,
-                                                       int64_t zs, const int* __restrict__ active) {
+                                                       int64_t zs, const int* __restrict__ active,
+                                                       tile::TileOrder ord) {
   using G = typename S::G;
   constexpr int K = S::K, TC = S::TC, n = S::n, NN = S::NN, NP = S::NP, NTH = S::NTH;
   __shared__ T pool[S::POOL];
@@ -410,11 +432,11 @@ __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, 
   __shared__ T sD[NN];
   __shared__ T sTab[G::TABMAX];
   if (active && !active[blockIdx.z]) return;
+  int tbx, tby;
+  if (!tile::tile_of_block(ord, blockIdx.x, tbx, tby)) return;
   x += blockIdx.z * zs;
   b += blockIdx.z * zs;
   xout += blockIdx.z * zs;
-  int tbx, tby;
-  tile::xcd_tile(tbx, tby);
   const int cx0 = tbx * TC, cy0 = tby * TC;
   const int x0 = (cx0 - 1) * K, y0 = (cy0 - 1) * K;  // residual tile origin (a vertex node)
   T* sX = pool;
@@ -425,6 +447,20 @@ __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, 
   for (int e = threadIdx.x; e < 4 * NN; e += NTH) sQ[e] = Qg[e];
   for (int e = threadIdx.x; e < 4 * n; e += NTH) sLam[e] = lamg[e];
   for (int e = threadIdx.x; e < NN; e += NTH) sD[e] = T(1) / (lamg[e % n] + lamg[e / n]);  // [ap][c]
+  // b on the residual tile, loaded now so that its latency overlaps the passes
+  T bv[G::NI][G::RW * K];
+#pragma unroll
+  for (int q = 0; q < G::NI; ++q) {
+    const int it = threadIdx.x + q * NTH;
+    const int cg = it / G::TX, l = it - cg * G::TX;
+    const int gx = x0 + l;
+#pragma unroll
+    for (int w = 0; w < G::RW * K; ++w) {
+      const int gy = y0 + cg * G::RW * K + w;
+      const bool inner = it < G::NIT_Y && gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2;
+      bv[q][w] = inner ? b[(size_t)gy * n1 + gx] : T(0);
+    }
+  }
   T acc[G::NI][G::RW * K];
   __syncthreads();
   op_tile_any<T, G>(sX, sT, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
@@ -439,8 +475,17 @@ __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, 
     for (int w = 0; w < G::RW * K; ++w) {
       const int rt = cg * G::RW * K + w, gy = y0 + rt;
       const bool inner = gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2;
-      sRr[rt * G::TX + l] = inner ? b[(size_t)gy * n1 + gx] - acc[q][w] : T(0);
+      sRr[rt * G::TX + l] = inner ? bv[q][w] - acc[q][w] : T(0);
     }
+  }
+  // x at the owned nodes, from the staged tile before the patch solves reuse it
+  constexpr int OW = TC * K + 1, NG = (OW * OW + NTH - 1) / NTH;
+  T xv[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int e = threadIdx.x + q * NTH;
+    const int jj = e / OW, ii = e - jj * OW;
+    xv[q] = e < OW * OW ? sX[(jj + K + G::H) * G::RX + ii + K + G::H] : T(0);
   }
   __syncthreads();
   const bool interior = cx0 >= 2 && cx0 + TC <= N - 2 && cy0 >= 2 && cy0 + TC <= N - 2;
@@ -450,11 +495,13 @@ __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, 
   else
     patch_solves<T, S, false>(sRr, sA, Qg, sQ, sLam, sD, N, cx0, cy0);
   // owned DoFs: x + omega * (sum of the covering patches' corrections)
-  constexpr int OW = TC * K + 1;
   const int gx0 = cx0 * K, gy0 = cy0 * K;
   const int gx1 = (cx0 + TC >= N) ? n1 : (cx0 + TC) * K;
   const int gy1 = (cy0 + TC >= N) ? n1 : (cy0 + TC) * K;
-  for (int e = threadIdx.x; e < OW * OW; e += NTH) {
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int e = threadIdx.x + q * NTH;
+    if (e >= OW * OW) break;
     const int jj = e / OW, ii = e - jj * OW;
     const int gx = gx0 + ii, gy = gy0 + jj;
     if (gx >= gx1 || gy >= gy1) continue;
@@ -475,7 +522,7 @@ __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, 
         a += sA[p * NN + r * n + c];
       }
     }
-    xout[idx] = x[idx] + omega * a;
+    xout[idx] = xv[q] + omega * a;
   }
 }
 
@@ -495,8 +542,14 @@ hipError_t avs2d_tc(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T*
   using S = SmGeo<T, K, TC, 256>;
   const int n1 = K * N + 1;
   const int nt = (N + TC - 1) / TC;
-  avs2d_kernel<T, S><<<dim3(nt, nt, nsys), S::NTH, 0, s>>>(x, b, xout, N, n1, c.tab, c.nclass, c.left, c.right0,
-                                                           c.periodic, e.Q, e.lam, omega, zs, active);
+  // interior: residual tile in the periodic row classes and every patch of the interior type
+  auto in = [&](int bt) {
+    const int c0 = bt * TC, o = (c0 - 1) * K;
+    return c.periodic && o >= c.left && o + (TC + 2) * K <= c.right0 && c0 >= 2 && c0 + TC <= N - 2;
+  };
+  const tile::TileOrder ord = tile::make_order(nt, nt, in, in);
+  avs2d_kernel<T, S><<<dim3(tile::order_blocks(ord), 1, nsys), S::NTH, 0, s>>>(
+      x, b, xout, N, n1, c.tab, c.nclass, c.left, c.right0, c.periodic, e.Q, e.lam, omega, zs, active, ord);
   return hipGetLastError();
 }
 

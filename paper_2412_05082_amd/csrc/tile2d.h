@@ -34,6 +34,90 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
   by = logical / gx;
 }
 
+// Block-to-tile order of a launch.  Tiles outside the rectangle
+// [bx_lo, bx_hi] x [by_lo, by_hi] (those that need per-lane row classes or
+// boundary patches, and run slower) take the first block indices so that
+// they start first and do not trail the launch.  The interior rectangle
+// follows, each XCD walking one contiguous band of it (row-major), which
+// keeps the halos that neighbouring tiles share in one L2.  Blocks
+// [nb, nbp) pad the ring to a multiple of 8 and do nothing.
+struct TileOrder {
+  int tx = 0, ty = 0, bx_lo = 0, bx_hi = -1, by_lo = 0, by_hi = -1, nb = 0, nbp = 0;
+};
+
+// in[b] for b = 0..n-1 must be true exactly on one range; returns it (lo > hi if empty)
+template <class F>
+inline void interior_range(int n, F in, int& lo, int& hi) {
+  lo = 0;
+  hi = -1;
+  int b = 0;
+  while (b < n && !in(b)) ++b;
+  lo = b;
+  while (b < n && in(b)) ++b;
+  hi = b - 1;
+  if (lo > hi) {
+    lo = 0;
+    hi = -1;
+  }
+}
+
+template <class FX, class FY>
+inline TileOrder make_order(int tx, int ty, FX xin, FY yin) {
+  TileOrder o;
+  o.tx = tx;
+  o.ty = ty;
+  interior_range(tx, xin, o.bx_lo, o.bx_hi);
+  interior_range(ty, yin, o.by_lo, o.by_hi);
+  if (o.bx_lo > o.bx_hi || o.by_lo > o.by_hi) {
+    o.bx_lo = o.by_lo = 0;
+    o.bx_hi = o.by_hi = -1;
+  }
+  const int ni = (o.bx_hi - o.bx_lo + 1) * (o.by_hi - o.by_lo + 1);
+  o.nb = tx * ty - ni;
+  o.nbp = (o.nb + 7) & ~7;
+  return o;
+}
+inline int order_blocks(const TileOrder& o) {
+  return o.nbp + (o.bx_hi - o.bx_lo + 1) * (o.by_hi - o.by_lo + 1);
+}
+
+__host__ __device__ inline bool tile_of_block(const TileOrder& o, int L, int& bx, int& by) {
+  const int iw = o.bx_hi - o.bx_lo + 1, ih = o.by_hi - o.by_lo + 1;
+  if (L < o.nb) {
+    if (iw <= 0) {
+      bx = L % o.tx;
+      by = L / o.tx;
+      return true;
+    }
+    const int ntop = o.by_lo * o.tx;
+    if (L < ntop) {
+      by = L / o.tx;
+      bx = L - by * o.tx;
+      return true;
+    }
+    L -= ntop;
+    const int side = o.tx - iw, nmid = ih * side;
+    if (L < nmid) {
+      const int r = L / side, c = L - r * side;
+      by = o.by_lo + r;
+      bx = c < o.bx_lo ? c : c + iw;
+      return true;
+    }
+    L -= nmid;
+    by = o.by_hi + 1 + L / o.tx;
+    bx = L % o.tx;
+    return true;
+  }
+  if (L < o.nbp) return false;
+  const int Li = L - o.nbp, T = iw * ih;
+  if (Li >= T) return false;
+  const int c = Li & 7, q = Li >> 3;
+  const int logical = c * (T >> 3) + (c < (T & 7) ? c : (T & 7)) + q;
+  bx = o.bx_lo + logical % iw;
+  by = o.by_lo + logical / iw;
+  return true;
+}
+
 // Structural band of a row at position p in its cell (p = 0: vertex node)
 // for the three 1D factors, OP = 0 (M), 1 (L), 2 (B): M and L couple the
 // nodes of the one (p > 0) or two (p = 0) cells containing the row; B

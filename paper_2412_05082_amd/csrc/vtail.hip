@@ -17,7 +17,27 @@
 namespace c0ip {
 namespace {
 
-constexpr int kTailThreads = 512;
+constexpr int kTailThreads = 1024;
+
+// dst[0..n) = src[0..n), four loads in flight per thread
+template <typename Td, typename Ts>
+__device__ __forceinline__ void t_copy(Td* __restrict__ dst, const Ts* __restrict__ src, int n) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += 4 * kTailThreads) {
+    Ts v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * kTailThreads;
+      v[u] = e < n ? src[e] : Ts(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * kTailThreads;
+      if (e < n) dst[e] = (Td)v[u];
+    }
+  }
+}
+
+__device__ __forceinline__ int clampn(int v, int n1) { return v < 0 ? 0 : (v > n1 - 1 ? n1 - 1 : v); }
 
 __device__ __forceinline__ int rclass(int g, int n1, int k, int left, int right0, int periodic) {
   if (!periodic) return g;
@@ -26,10 +46,6 @@ __device__ __forceinline__ int rclass(int g, int n1, int k, int left, int right0
   return 2 * left + g % k;
 }
 __device__ __forceinline__ int pvariant(int v, int N) { return (v == 1 ? 1 : 0) | (v == N - 1 ? 2 : 0); }
-template <int K> __device__ constexpr int mlo(int p) { return p == 0 ? -K : -p; }
-template <int K> __device__ constexpr int mhi(int p) { return p == 0 ? K : K - p; }
-template <int K> __device__ constexpr int blo(int p) { return p == 0 ? -2 * K : -K - p; }
-template <int K> __device__ constexpr int bhi(int p) { return p == 0 ? 2 * K : 2 * K - p; }
 
 // LDS layout (element offsets; the same function sizes the launch).  x and
 // b live on every level; r and the sweep/patch scratch only on the level
@@ -80,41 +96,50 @@ __host__ __device__ inline TailLayout tail_layout(int k, int LT, const int* ncla
   return L;
 }
 
+// y = A x (b == nullptr) or y = b - A x (0 on the boundary).  Every tap
+// runs over the widest band with the table's zero entries outside a row's
+// structural band (and outside the mesh), so the loops have fixed trip
+// counts; indices past the mesh edge are clamped (their coefficient is 0).
 template <typename T, int K>
 __device__ void t_apply(int N, const T* x, const T* b, T* y, T* U, T* V, T* W, const T* tab, int nclass, int left,
                         int right0, int periodic) {
-  const int n1 = K * N + 1, nn = n1 * n1, Wd = 4 * K + 1, H = 2 * K;
+  const int n1 = K * N + 1, nn = n1 * n1;
+  constexpr int Wd = 4 * K + 1, H = 2 * K;
   for (int e = threadIdx.x; e < nn; e += kTailThreads) {
-    const int i = e % n1, j = e / n1;
-    const int cls = rclass(i, n1, K, left, right0, periodic), p = i % K;
+    const int j = e / n1, i = e - j * n1;
+    const int cls = rclass(i, n1, K, left, right0, periodic);
     const T* cM = tab + cls * Wd + H;
     const T* cL = tab + (nclass + cls) * Wd + H;
     const T* cB = tab + (2 * nclass + cls) * Wd + H;
-    const T* row = x + j * n1 + i;
+    const T* row = x + j * n1;
     T u = 0, v = 0, w = 0;
-    for (int o = mlo<K>(p); o <= mhi<K>(p); ++o)
-      if (i + o >= 0 && i + o < n1) {
-        u += cM[o] * row[o];
-        v += cL[o] * row[o];
+#pragma unroll
+    for (int o = -2 * K; o <= 2 * K; ++o) {
+      const T xv = row[clampn(i + o, n1)];
+      if (o >= -K && o <= K) {
+        u += cM[o] * xv;
+        v += cL[o] * xv;
       }
-    for (int o = blo<K>(p); o <= bhi<K>(p); ++o)
-      if (i + o >= 0 && i + o < n1) w += cB[o] * row[o];
+      w += cB[o] * xv;
+    }
     U[e] = u;
     V[e] = v;
     W[e] = w;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < nn; e += kTailThreads) {
-    const int i = e % n1, j = e / n1;
-    const int cls = rclass(j, n1, K, left, right0, periodic), p = j % K;
+    const int j = e / n1, i = e - j * n1;
+    const int cls = rclass(j, n1, K, left, right0, periodic);
     const T* cM = tab + cls * Wd + H;
     const T* cL = tab + (nclass + cls) * Wd + H;
     const T* cB = tab + (2 * nclass + cls) * Wd + H;
     T acc = 0;
-    for (int o = mlo<K>(p); o <= mhi<K>(p); ++o)
-      if (j + o >= 0 && j + o < n1) acc += cM[o] * W[e + o * n1] + 2 * cL[o] * V[e + o * n1];
-    for (int o = blo<K>(p); o <= bhi<K>(p); ++o)
-      if (j + o >= 0 && j + o < n1) acc += cB[o] * U[e + o * n1];
+#pragma unroll
+    for (int o = -2 * K; o <= 2 * K; ++o) {
+      const int q = clampn(j + o, n1) * n1 + i;
+      if (o >= -K && o <= K) acc += cM[o] * W[q] + 2 * cL[o] * V[q];
+      acc += cB[o] * U[q];
+    }
     if (b) {
       const bool bnd = i == 0 || j == 0 || i == n1 - 1 || j == n1 - 1;
       y[e] = bnd ? T(0) : b[e] - acc;
@@ -125,60 +150,69 @@ __device__ void t_apply(int N, const T* x, const T* b, T* y, T* U, T* V, T* W, c
   __syncthreads();
 }
 
-// Patch solves of all (N-1)^2 patches of the level from r, into PR.
+// Patch solves of all (N-1)^2 patches of the level from r, into PR
+// (patch-major, n x n each): forward along x, along y (with the division
+// by lambda_x + lambda_y) and back, back along x; one patch row or column
+// per thread, in place.
 template <typename T, int K>
 __device__ void t_patches(int N, const T* r, T* PR, const T* Q, const T* lam) {
   constexpr int n = 2 * K - 1, NN = n * n;
-  const int n1 = K * N + 1, NP = N - 1;
-  for (int pi = threadIdx.x; pi < NP * NP; pi += kTailThreads) {
-    const int vx = pi % NP + 1, vy = pi / NP + 1;
+  const int n1 = K * N + 1, NP = N - 1, items = NP * NP * n;
+  for (int it = threadIdx.x; it < items; it += kTailThreads) {
+    const int pi = it / n, a = it - pi * n;
+    const int vy = pi / NP + 1, vx = pi - (vy - 1) * NP + 1;
     const T* qx = Q + pvariant(vx, N) * NN;
-    const T* qy = Q + pvariant(vy, N) * NN;
-    const T* lx = lam + pvariant(vx, N) * n;
-    const T* ly = lam + pvariant(vy, N) * n;
-    const T* src = r + ((vy - 1) * K + 1) * n1 + (vx - 1) * K + 1;
-    T a[NN], t[NN];
+    const T* src = r + ((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1;
+    T in[n];
 #pragma unroll
-    for (int aa = 0; aa < n; ++aa)
+    for (int c = 0; c < n; ++c) in[c] = src[c];
 #pragma unroll
-      for (int c = 0; c < n; ++c) a[aa * n + c] = src[aa * n1 + c];
+    for (int c = 0; c < n; ++c) {
+      T s = 0;
 #pragma unroll
-    for (int aa = 0; aa < n; ++aa)  // Qx^T along x
+      for (int cp = 0; cp < n; ++cp) s += qx[cp * n + c] * in[cp];
+      PR[pi * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < items; it += kTailThreads) {
+    const int pi = it / n, c = it - pi * n;
+    const int vy = pi / NP + 1, vx = pi - (vy - 1) * NP + 1;
+    const int tx = pvariant(vx, N), ty = pvariant(vy, N);
+    const T* qy = Q + ty * NN;
+    T col[n], t[n];
 #pragma unroll
-      for (int c = 0; c < n; ++c) {
-        T s = 0;
+    for (int a = 0; a < n; ++a) col[a] = PR[pi * NN + a * n + c];
 #pragma unroll
-        for (int cp = 0; cp < n; ++cp) s += qx[cp * n + c] * a[aa * n + cp];
-        t[aa * n + c] = s;
-      }
+    for (int ap = 0; ap < n; ++ap) {
+      T s = 0;
 #pragma unroll
-    for (int ap = 0; ap < n; ++ap)  // Qy^T along y, divide
+      for (int a = 0; a < n; ++a) s += qy[a * n + ap] * col[a];
+      t[ap] = s / (lam[tx * n + c] + lam[ty * n + ap]);
+    }
 #pragma unroll
-      for (int c = 0; c < n; ++c) {
-        T s = 0;
+    for (int a = 0; a < n; ++a) {
+      T s = 0;
 #pragma unroll
-        for (int aa = 0; aa < n; ++aa) s += qy[aa * n + ap] * t[aa * n + c];
-        a[ap * n + c] = s / (lx[c] + ly[ap]);
-      }
+      for (int ap = 0; ap < n; ++ap) s += qy[a * n + ap] * t[ap];
+      PR[pi * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < items; it += kTailThreads) {
+    const int pi = it / n, a = it - pi * n;
+    const int vy = pi / NP + 1, vx = pi - (vy - 1) * NP + 1;
+    const T* qx = Q + pvariant(vx, N) * NN;
+    T in[n];
 #pragma unroll
-    for (int aa = 0; aa < n; ++aa)  // Qy along y
+    for (int c = 0; c < n; ++c) in[c] = PR[pi * NN + a * n + c];
 #pragma unroll
-      for (int c = 0; c < n; ++c) {
-        T s = 0;
+    for (int cp = 0; cp < n; ++cp) {
+      T s = 0;
 #pragma unroll
-        for (int ap = 0; ap < n; ++ap) s += qy[aa * n + ap] * a[ap * n + c];
-        t[aa * n + c] = s;
-      }
-    T* dst = PR + pi * NN;
-#pragma unroll
-    for (int aa = 0; aa < n; ++aa)  // Qx along x
-#pragma unroll
-      for (int cp = 0; cp < n; ++cp) {
-        T s = 0;
-#pragma unroll
-        for (int c = 0; c < n; ++c) s += qx[cp * n + c] * t[aa * n + c];
-        dst[aa * n + cp] = s;
-      }
+      for (int c = 0; c < n; ++c) s += qx[cp * n + c] * in[c];
+      PR[pi * NN + a * n + cp] = s;
+    }
   }
   __syncthreads();
 }
@@ -277,20 +311,17 @@ __global__ __launch_bounds__(kTailThreads) void vtail_kernel(TailParams<T> P, Ta
   T* S = reinterpret_cast<T*>(smem);
   double* A0 = reinterpret_cast<double*>(smem) + L.a0;
   constexpr int n = 2 * K - 1, n0 = n * n;
-  for (int l = 0; l <= top; ++l) {
-    const int nt = 3 * P.nclass[l] * (4 * K + 1);
-    for (int e = threadIdx.x; e < nt; e += kTailThreads) S[L.tab[l] + e] = P.tab[l][e];
-    for (int e = threadIdx.x; e < 4 * n * n; e += kTailThreads) S[L.q[l] + e] = P.Q[l][e];
-    for (int e = threadIdx.x; e < 4 * n; e += kTailThreads) S[L.lam[l] + e] = P.lam[l][e];
-  }
-  for (int e = threadIdx.x; e < 2 * K * (K + 1); e += kTailThreads) S[L.pt + e] = P.ptab[e];
-  if (P.coarse_mode == 0)
-    for (int e = threadIdx.x; e < n0 * n0; e += kTailThreads) A0[e] = P.Ainv[e];
   {
     const int n1 = K * (2 << top) + 1;
-    const T* src = io.b[top] + (int64_t)sys * io.stride[top];
-    for (int e = threadIdx.x; e < n1 * n1; e += kTailThreads) S[L.b[top] + e] = src[e];
+    t_copy(S + L.b[top], io.b[top] + (int64_t)sys * io.stride[top], n1 * n1);
   }
+  for (int l = 0; l <= top; ++l) {
+    t_copy(S + L.tab[l], P.tab[l], 3 * P.nclass[l] * (4 * K + 1));
+    t_copy(S + L.q[l], P.Q[l], 4 * n * n);
+    t_copy(S + L.lam[l], P.lam[l], 4 * n);
+  }
+  t_copy(S + L.pt, P.ptab, 2 * K * (K + 1));
+  if (P.coarse_mode == 0) t_copy(A0, P.Ainv, n0 * n0);
   __syncthreads();
   const T om = P.omega;
   T* r = S + L.r;
@@ -355,8 +386,7 @@ __global__ __launch_bounds__(kTailThreads) void vtail_kernel(TailParams<T> P, Ta
   }
   {
     const int n1 = K * (2 << top) + 1;
-    T* dst = io.x[top] + (int64_t)sys * io.stride[top];
-    for (int e = threadIdx.x; e < n1 * n1; e += kTailThreads) dst[e] = S[L.x[top] + e];
+    t_copy(io.x[top] + (int64_t)sys * io.stride[top], S + L.x[top], n1 * n1);
   }
 }
 
