@@ -45,7 +45,36 @@ def parse():
     ap.add_argument("--only", default=None,
                     choices=["matvec_f64", "smoother_f64", "matvec_f32", "smoother_f32", "copy_f64"],
                     help="run only this kernel's timing loop (for counter collection) and print its ms")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="with --only smoother_*: fused smoother tile variant on the finest level")
     return ap.parse_args()
+
+
+# HBM traffic of the fused smoother, from the committed counter summary: one
+# row per tile variant, valid only for the kernel source it was measured on.
+COUNTERS = os.path.join(ROOT, "profiles", "avs2d_f32_2d_q3_512_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2412_05082_amd", "csrc", "op2d.hip")
+
+
+def measured_traffic(variant):
+    """Bytes per launch (FETCH_SIZE x copy factor + WRITE_SIZE) of the float32
+    fused smoother step with this tile variant, or None when the summary is
+    missing, has no row for it, or was taken on another version of the
+    kernel source."""
+    import hashlib
+    import re
+    try:
+        text = open(COUNTERS).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"kernel source sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != src:
+        return None
+    for row in re.finditer(r"^\| *variant (\d+) *\|.*\| *([0-9]+) *\| *$", text, re.M):
+        if int(row.group(1)) == variant:
+            return int(row.group(2))
+    return None
 
 
 def only_kernel(args):
@@ -66,6 +95,8 @@ def only_kernel(args):
     y = torch.zeros_like(x)
     pb = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F32)
     pb.autotune()
+    if args.variant is not None:
+        pb.set_variant(args.variant, dtype=P.C0IP_F32 if args.only.endswith("f32") else P.C0IP_F64)
     fn = {"matvec_f64": lambda: pb.apply_A(x, y), "matvec_f32": lambda: pb.apply_A(x, y),
           "smoother_f64": lambda: pb.smoother_step(b, x, y), "smoother_f32": lambda: pb.smoother_step(b, x, y),
           "copy_f64": lambda: y.copy_(x)}[args.only]
@@ -267,6 +298,8 @@ def main():
     # dominant kernel of the float32 V-cycle: the fused smoother step S(x, b)
     bytes_sm32 = 12.0 * n  # read x, read b, write x_out (float32)
     achieved = bytes_sm32 / (ms_smx32 * 1e-3) / 1e9
+    var32 = pmix.tuned_variant(dtype=P.C0IP_F32)
+    traffic = measured_traffic(var32)
     out = {
         "metric": "DoFs/s of C0IP mat-vec and patch smoother; FP32-vs-FP64 MG-GMRES solve time",
         "value": value,
@@ -305,9 +338,10 @@ def main():
         "tuned_tile_variant": {"f32": pmix.tuned_variant(dtype=P.C0IP_F32),
                                "f64": p64.tuned_variant(dtype=P.C0IP_F64)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "avs2d_kernel<float,3,8>: fused float32 smoother step S(x,b) "
-                               "(residual in LDS + patch solves), 12 B/DoF x 2,362,369 DoFs per launch"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"avs2d_kernel<float, k=3, tile variant {var32}>: fused float32 smoother step "
+                               f"S(x,b) (residual in LDS + patch solves), 12 B/DoF x {n} DoFs per launch; "
+                               f"traffic = HBM bytes per launch from FETCH_SIZE/WRITE_SIZE"},
     }
     if not args.no_batch:
         out["config_batched"] = bench_batch(torch, P)

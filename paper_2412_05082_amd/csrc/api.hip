@@ -67,6 +67,7 @@ template <typename T>
 struct LevelWork {
   DevBuf<T> tab, Q, lam, ptab;  // coefficient table, eigenbases, prolongation table
   DevBuf<T> x, b, r, scratch;   // V-cycle vectors and transfer scratch
+  DevBuf<T> t;                  // 2D: second iterate buffer (smoothing steps are out of place)
   c0ip::LevelCoef<T> coef;
   c0ip::LevelEig<T> eig;
   int avs_variant = 0;  // tile variant of the fused smoother (set by c0ip_autotune)
@@ -113,6 +114,8 @@ struct c0ip_problem {
   void smooth_from(int l, const T* b, T* from, T* x, int steps);
   template <typename T>
   void mg_level(int l, const T* b, T* x);
+  template <typename T>
+  void mg_level2d(int l, const T* b, T* x);
   // top level of the single-workgroup tail V-cycle in precision T (-1: none)
   int tailLT[2] = {-2, -2};
   template <typename T>
@@ -155,6 +158,7 @@ void c0ip_problem::prepare(int l) {
   w.x.alloc(L_.ntot);
   w.b.alloc(L_.ntot);
   w.r.alloc(L_.ntot);
+  if (dim == 2) w.t.alloc(L_.ntot);
   if (l > 0) {
     const int64_t nf = L_.n1, nc = lv[l - 1]->n1;
     const int64_t s = dim == 2 ? nf * nc : 2 * nf * nf * nc;
@@ -268,6 +272,50 @@ void c0ip_problem::run_tail(const T* b, T* x) {
   check(c0ip::launch_vtail<T>(k, P, io, 1, stream), "tail V-cycle");
 }
 
+// One 2D level of Algorithm 1 with out-of-place smoothing steps.  The
+// iterate alternates between x and the level's t buffer; the pre-smoothing
+// result lands in A, chosen so that the post-smoothing steps end in x.  The
+// first post-smoothing step starts from A + P e inside the fused smoother
+// (no separate prolongation pass).
+template <typename T>
+void c0ip_problem::mg_level2d(int l, const T* b, T* x) {
+  LevelWork<T>& w = work<T>(l);
+  LevelWork<T>& wc = work<T>(l - 1);
+  const int Nl = lv[l]->N, pre = mg.pre_steps, post = mg.post_steps;
+  const T om = (T)mg.omega;
+  T* A = (post % 2 == 1) ? w.t.p : x;
+  T* B = (A == x) ? w.t.p : x;
+  if (pre == 0) {
+    check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), A, stream), "fill");
+  } else {
+    T* cur = (pre % 2 == 1) ? A : B;
+    check(c0ip::launch_patch2d<T>(k, Nl, w.eig, b, nullptr, cur, om, stream), "smoother");
+    for (int s = 1; s < pre; ++s) {
+      T* nxt = (cur == A) ? B : A;
+      check(c0ip::launch_avs2d<T>(k, Nl, w.coef, w.eig, cur, b, nxt, om, stream, 1, 0, nullptr, w.avs_variant),
+            "fused smoother");
+      cur = nxt;
+    }
+  }
+  check(c0ip::launch_apply2d<T, T>(k, Nl, w.coef, A, b, w.r.p, stream), "residual");
+  check(c0ip::launch_restrict2d<T>(k, lv[l - 1]->N, w.ptab.p, w.r.p, wc.b.p, stream), "restrict");
+  mg_level<T>(l - 1, wc.b.p, wc.x.p);
+  if (post == 0) {
+    check(c0ip::launch_prolong2d<T>(k, lv[l - 1]->N, w.ptab.p, wc.x.p, A, x, stream), "prolong");
+    return;
+  }
+  check(c0ip::launch_avs2d<T>(k, Nl, w.coef, w.eig, A, b, B, om, stream, 1, 0, nullptr, w.avs_variant, wc.x.p,
+                              w.ptab.p),
+        "prolongation + fused smoother");
+  T* cur = B;
+  for (int s = 1; s < post; ++s) {
+    T* nxt = (cur == A) ? B : A;
+    check(c0ip::launch_avs2d<T>(k, Nl, w.coef, w.eig, cur, b, nxt, om, stream, 1, 0, nullptr, w.avs_variant),
+          "fused smoother");
+    cur = nxt;
+  }
+}
+
 // x = MG_l(0, b) (Algorithm 1, returning right after the coarse solve).
 template <typename T>
 void c0ip_problem::mg_level(int l, const T* b, T* x) {
@@ -286,15 +334,15 @@ void c0ip_problem::mg_level(int l, const T* b, T* x) {
   }
   LevelWork<T>& w = work<T>(l);
   LevelWork<T>& wc = work<T>(l - 1);
+  if (dim == 2) {
+    mg_level2d<T>(l, b, x);
+    return;
+  }
   smooth<T>(l, b, x, mg.pre_steps, true);
   check(c0ip::launch_apply<T, T>(dim, k, lv[l]->N, w.coef, x, b, w.r.p, stream), "residual");
   check(c0ip::launch_restrict<T>(dim, k, lv[l - 1]->N, w.ptab.p, w.r.p, wc.b.p, w.scratch.p, stream), "restrict");
   mg_level<T>(l - 1, wc.b.p, wc.x.p);
-  if (dim == 2 && mg.post_steps > 0) {
-    // r_l = x + P e (out of place), then the fused steps bring the result back to x
-    check(c0ip::launch_prolong2d<T>(k, lv[l - 1]->N, w.ptab.p, wc.x.p, x, w.r.p, stream), "prolong");
-    smooth_from<T>(l, b, w.r.p, x, mg.post_steps);
-  } else {
+  {
     check(c0ip::launch_prolong_add<T>(dim, k, lv[l - 1]->N, w.ptab.p, wc.x.p, x, w.scratch.p, stream), "prolong");
     smooth<T>(l, b, x, mg.post_steps, false);
   }

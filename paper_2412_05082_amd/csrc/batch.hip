@@ -285,8 +285,8 @@ struct Group {
   std::vector<int> members;  // system indices, slot order (descending L)
   std::vector<int> A;        // A[l] = systems with L_s >= l (a prefix of the slots)
   c0ip_problem* proto = nullptr;  // tables for levels 0..Lmax
-  std::vector<std::unique_ptr<Buf<float>>> x32, b32, r32;
-  std::vector<std::unique_ptr<Buf<double>>> x64, b64, r64;
+  std::vector<std::unique_ptr<Buf<float>>> x32, b32, r32, t32;
+  std::vector<std::unique_ptr<Buf<double>>> x64, b64, r64, t64;
   std::vector<std::unique_ptr<Buf<double>>> W;  // A z of systems whose finest level is l
   Buf<int> mask;
 };
@@ -334,11 +334,11 @@ template <typename T>
 static Buf<T>& lvbuf(Group& g, int which, int l);
 template <>
 Buf<float>& lvbuf<float>(Group& g, int which, int l) {
-  return which == 0 ? *g.x32[l] : (which == 1 ? *g.b32[l] : *g.r32[l]);
+  return which == 0 ? *g.x32[l] : (which == 1 ? *g.b32[l] : (which == 2 ? *g.r32[l] : *g.t32[l]));
 }
 template <>
 Buf<double>& lvbuf<double>(Group& g, int which, int l) {
-  return which == 0 ? *g.x64[l] : (which == 1 ? *g.b64[l] : *g.r64[l]);
+  return which == 0 ? *g.x64[l] : (which == 1 ? *g.b64[l] : (which == 2 ? *g.r64[l] : *g.t64[l]));
 }
 
 // Algorithm 1 for every system of the group at once (see the file comment).
@@ -360,19 +360,23 @@ void c0ip_batch::vcycle(Group& g) {
     T *x = lvbuf<T>(g, 0, l).p, *b = lvbuf<T>(g, 1, l).p, *r = lvbuf<T>(g, 2, l).p;
     const auto& coef = c0ip_internal_coef<T>(g.proto, l);
     const auto& eig = c0ip_internal_eig<T>(g.proto, l);
+    // the iterate alternates between x and t; the pre-smoothing result lands
+    // in A, chosen so that the post-smoothing steps end in x
+    T* A = (post % 2 == 1) ? lvbuf<T>(g, 3, l).p : x;
+    T* B = (A == x) ? lvbuf<T>(g, 3, l).p : x;
     if (pre == 0) {
-      hchk(launch_fill_t<T>(nA * nl, T(0), x, s), "fill");
+      hchk(launch_fill_t<T>(nA * nl, T(0), A, s), "fill");
     } else {
-      hchk(launch_patch2d<T>(k, Nl, eig, b, nullptr, x, om, s, nA, nl, mask), "patch");
-      T *cur = x, *oth = r;
+      T* cur = (pre % 2 == 1) ? A : B;
+      hchk(launch_patch2d<T>(k, Nl, eig, b, nullptr, cur, om, s, nA, nl, mask), "patch");
       for (int st = 1; st < pre; ++st) {
-        hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, oth, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
-           "fused smoother");
-        std::swap(cur, oth);
+        T* nxt = (cur == A) ? B : A;
+        hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, nxt, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
+             "fused smoother");
+        cur = nxt;
       }
-      if (cur != x) hchk(hipMemcpyAsync(x, cur, sizeof(T) * nA * nl, hipMemcpyDeviceToDevice, s), "copy");
     }
-    hchk(launch_apply2d<T, T>(k, Nl, coef, x, b, r, s, nA, nl, mask), "residual");
+    hchk(launch_apply2d<T, T>(k, Nl, coef, A, b, r, s, nA, nl, mask), "residual");
     hchk(launch_restrict2d<T>(k, Nl / 2, c0ip_internal_ptab<T>(g.proto, l), r, lvbuf<T>(g, 1, l - 1).p, s, nA, nl,
                               n1(l - 1), mask),
          "restrict");
@@ -403,21 +407,27 @@ void c0ip_batch::vcycle(Group& g) {
     if (nA == 0) continue;
     const int Nl = 2 << l;
     const int64_t nl = n1(l);
-    T *x = lvbuf<T>(g, 0, l).p, *b = lvbuf<T>(g, 1, l).p, *r = lvbuf<T>(g, 2, l).p;
+    T *x = lvbuf<T>(g, 0, l).p, *b = lvbuf<T>(g, 1, l).p;
     const auto& coef = c0ip_internal_coef<T>(g.proto, l);
     const auto& eig = c0ip_internal_eig<T>(g.proto, l);
-    // r = x + P e, then fused steps alternate r -> x -> r ...; the result ends in x
-    T* cur = post > 0 ? r : x;
-    hchk(launch_prolong2d<T>(k, Nl / 2, c0ip_internal_ptab<T>(g.proto, l), lvbuf<T>(g, 0, l - 1).p, x, cur, s, nA,
-                             n1(l - 1), nl, mask),
-         "prolong");
-    T* oth = post > 0 ? x : r;
-    for (int st = 0; st < post; ++st) {
-      hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, oth, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
-           "fused smoother");
-      std::swap(cur, oth);
+    const T* ptab = c0ip_internal_ptab<T>(g.proto, l);
+    T* A = (post % 2 == 1) ? lvbuf<T>(g, 3, l).p : x;
+    T* B = (A == x) ? lvbuf<T>(g, 3, l).p : x;
+    if (post == 0) {
+      hchk(launch_prolong2d<T>(k, Nl / 2, ptab, lvbuf<T>(g, 0, l - 1).p, A, x, s, nA, n1(l - 1), nl, mask), "prolong");
+      continue;
     }
-    if (cur != x) hchk(hipMemcpyAsync(x, cur, sizeof(T) * nA * nl, hipMemcpyDeviceToDevice, s), "copy");
+    // first post-smoothing step from A + P e (fused), then alternate; ends in x
+    hchk(launch_avs2d<T>(k, Nl, coef, eig, A, b, B, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l),
+                         lvbuf<T>(g, 0, l - 1).p, ptab, n1(l - 1)),
+         "prolongation + fused smoother");
+    T* cur = B;
+    for (int st = 1; st < post; ++st) {
+      T* nxt = (cur == A) ? B : A;
+      hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, nxt, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
+           "fused smoother");
+      cur = nxt;
+    }
   }
 }
 
@@ -586,6 +596,8 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
           g.x32.emplace_back(new Buf<float>());
           g.b32.emplace_back(new Buf<float>());
           g.r32.emplace_back(new Buf<float>());
+          g.t32.emplace_back(new Buf<float>());
+          g.t32.back()->alloc(cnt);
           g.x32.back()->alloc(cnt);
           g.b32.back()->alloc(cnt);
           g.r32.back()->alloc(cnt);
@@ -593,6 +605,8 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
           g.x64.emplace_back(new Buf<double>());
           g.b64.emplace_back(new Buf<double>());
           g.r64.emplace_back(new Buf<double>());
+          g.t64.emplace_back(new Buf<double>());
+          g.t64.back()->alloc(cnt);
           g.x64.back()->alloc(cnt);
           g.b64.back()->alloc(cnt);
           g.r64.back()->alloc(cnt);

@@ -92,13 +92,14 @@ hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, con
 template <typename T>
 hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
                           hipStream_t s, int nsys = 1, int64_t zs = 0, const int* active = nullptr);
-// One fused smoothing step S(x, b) (residual in LDS, x_out may alias x only
-// if every tile reads x before any tile writes: it may NOT alias).
-// variant: tile-size variant (0 = default; see avs2d_variants).
+// One fused smoothing step S(x, b) (residual in LDS; x_out must not alias x).
+// variant: tile-size variant (0 = default; see avs2d_variants).  With ec:
+// the step starts from x + P ec instead (ec: coarse vector of the level
+// below, zc apart between systems; ptab: the embedding table).
 template <typename T>
 hipError_t launch_avs2d(int k, int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout,
                         T omega, hipStream_t s, int nsys = 1, int64_t zs = 0, const int* active = nullptr,
-                        int variant = 0);
+                        int variant = 0, const T* ec = nullptr, const T* ptab = nullptr, int64_t zc = 0);
 int avs2d_variants(int k);
 template <typename T>
 hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s, int nsys = 1,

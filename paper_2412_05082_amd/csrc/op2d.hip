@@ -297,11 +297,20 @@ template <> struct ApplyCfg<5> { using G = Geo<5, 8, 4, 256, 2, 2>; };
 template <> struct ApplyCfg<6> { using G = Geo<6, 8, 4, 256, 2, 2>; };
 template <> struct ApplyCfg<7> { using G = Geo<7, 6, 4, 256, 2, 2>; };
 
-template <typename Tin, typename T, int K>
-hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s, int nsys,
+// Small meshes (fewer big tiles than compute units) are latency bound: a
+// one-wave workgroup per small tile shortens each block's chain of passes
+// and spreads the mesh over more compute units.
+template <int K> struct ApplyCfgSmall;
+template <> struct ApplyCfgSmall<2> { using G = Geo<2, 6, 6, 64, 2, 2>; };
+template <> struct ApplyCfgSmall<3> { using G = Geo<3, 4, 4, 64, 2, 2>; };
+template <> struct ApplyCfgSmall<4> { using G = Geo<4, 4, 4, 64, 2, 2>; };
+template <> struct ApplyCfgSmall<5> { using G = Geo<5, 2, 2, 64, 2, 2>; };
+template <> struct ApplyCfgSmall<6> { using G = Geo<6, 2, 2, 64, 2, 2>; };
+template <> struct ApplyCfgSmall<7> { using G = Geo<7, 2, 2, 64, 2, 2>; };
+
+template <typename Tin, typename T, class G>
+hipError_t apply2d_g(int n1, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s, int nsys,
                      int64_t zs, const int* active) {
-  using G = typename ApplyCfg<K>::G;
-  const int n1 = K * N + 1;
   const int tx = (n1 + G::TX - 1) / G::TX, ty = (n1 + G::TY - 1) / G::TY;
   const tile::TileOrder ord = tile::make_order(
       tx, ty, [&](int bx) { return c.periodic && bx * G::TX >= c.left && bx * G::TX + G::TX <= c.right0; },
@@ -314,6 +323,16 @@ hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* 
     apply2d_kernel<Tin, T, G, false><<<grid, G::NTH, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left, c.right0,
                                                              c.periodic, zs, active, ord);
   return hipGetLastError();
+}
+
+template <typename Tin, typename T, int K>
+hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s, int nsys,
+                     int64_t zs, const int* active) {
+  using G = typename ApplyCfg<K>::G;
+  const int n1 = K * N + 1;
+  const int64_t big = (int64_t)((n1 + G::TX - 1) / G::TX) * ((n1 + G::TY - 1) / G::TY) * nsys;
+  if (big < 256) return apply2d_g<Tin, T, typename ApplyCfgSmall<K>::G>(n1, c, x, b, y, s, nsys, zs, active);
+  return apply2d_g<Tin, T, G>(n1, c, x, b, y, s, nsys, zs, active);
 }
 
 // ------------------------------------------------------------------ smoother
@@ -337,7 +356,12 @@ struct SmGeo {
   using G = Geo<K, TC + 2, TC + 2, NTH, 2, 2>;
   static constexpr int n = 2 * K - 1, NN = n * n, NP = TC + 1;
   static constexpr int SZA = G::RY * G::RX + G::RY * G::TX, SZB = NP * NP * NN;
+  // coarse nodes per side of the staged region, and the prolongation scratch
+  // (coarse values and their x-pass) placed after the staged x
+  static constexpr int CX = ((G::RX - 1) / (2 * K) + 2) * K + 1;
+  static constexpr int SZP = G::RY * G::RX + CX * CX + CX * G::RX;
   static constexpr int POOL = SZA > SZB ? SZA : SZB;
+  static constexpr int POOLP = POOL > SZP ? POOL : SZP;
   // eigenbasis through scalar registers when it fits 64 of them
   static constexpr bool QS = NN * (int)sizeof(T) / 4 <= 64;
 };
@@ -416,27 +440,81 @@ __device__ __forceinline__ void patch_solves(const T* __restrict__ sRr, T* __res
   __syncthreads();
 }
 
+// sX += (P ec) on the staged region (fine nodes [x0 - 2k, ..) x [y0 - 2k, ..)):
+// the coarse values covering it are staged in sC, interpolated along x into
+// sP, then along y (the 1D embedding table T[s][p][a]: coarse-cell basis a
+// at position p of fine cell 2 cc + s).  P ec is 0 on the mesh boundary.
+// Ends with a barrier.
 template <typename T, class S>
+__device__ __forceinline__ void prolong_into(T* __restrict__ sX, T* __restrict__ sC, T* __restrict__ sP,
+                                             T* __restrict__ sPT, const T* __restrict__ ec,
+                                             const T* __restrict__ ptab, int nf, int x0, int y0) {
+  using G = typename S::G;
+  constexpr int K = S::K, CX = S::CX, RX = G::RX, RY = G::RY, NTH = S::NTH, NT = 2 * K * (K + 1);
+  const int nc = (nf - 1) / 2 + 1;
+  const int f0x = x0 - G::H, f0y = y0 - G::H;
+  const int cxl = ((f0x > 0 ? f0x : 0) / K >> 1) * K, cyl = ((f0y > 0 ? f0y : 0) / K >> 1) * K;
+  for (int e = threadIdx.x; e < CX * CX; e += NTH) {
+    const int r = e / CX, c = e - r * CX;
+    const int gy = cyl + r, gx = cxl + c;
+    sC[e] = (gy < nc && gx < nc) ? ec[(size_t)gy * nc + gx] : T(0);
+  }
+  for (int e = threadIdx.x; e < NT; e += NTH) sPT[e] = ptab[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < CX * RX; e += NTH) {
+    const int r = e / RX, c = e - r * RX;
+    const int f = f0x + c;
+    T v = 0;
+    if (f >= 1 && f <= nf - 2) {
+      const int cf = f / K, p = f - cf * K, cc = cf >> 1, sh = cf & 1;
+      const T* tb = sPT + (sh * K + p) * (K + 1);
+      const T* src = sC + r * CX + cc * K - cxl;
+#pragma unroll
+      for (int a = 0; a <= K; ++a) v += tb[a] * src[a];
+    }
+    sP[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < RY * RX; e += NTH) {
+    const int r = e / RX, c = e - r * RX;
+    const int f = f0y + r;
+    if (f >= 1 && f <= nf - 2) {
+      const int cf = f / K, p = f - cf * K, cc = cf >> 1, sh = cf & 1;
+      const T* tb = sPT + (sh * K + p) * (K + 1);
+      const T* src = sP + (cc * K - cyl) * RX + c;
+      T v = 0;
+#pragma unroll
+      for (int a = 0; a <= K; ++a) v += tb[a] * src[a * RX];
+      sX[e] += v;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, class S, bool PRO>
 __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, const T* __restrict__ b,
                                                        T* __restrict__ xout, int N, int n1, const T* __restrict__ tab,
                                                        int nclass, int left, int right0, int periodic,
                                                        const T* __restrict__ Qg, const T* __restrict__ lamg, T omega,
                                                        int64_t zs, const int* __restrict__ active,
-                                                       tile::TileOrder ord) {
+                                                       tile::TileOrder ord, const T* __restrict__ ec,
+                                                       const T* __restrict__ ptab, int64_t zc) {
   using G = typename S::G;
   constexpr int K = S::K, TC = S::TC, n = S::n, NN = S::NN, NP = S::NP, NTH = S::NTH;
-  __shared__ T pool[S::POOL];
+  __shared__ T pool[PRO ? S::POOLP : S::POOL];
   __shared__ T sRr[G::TY * G::TX];
   __shared__ T sQ[4 * NN];
   __shared__ T sLam[4 * n];
   __shared__ T sD[NN];
   __shared__ T sTab[G::TABMAX];
+  __shared__ T sPT[PRO ? 2 * K * (K + 1) : 1];
   if (active && !active[blockIdx.z]) return;
   int tbx, tby;
   if (!tile::tile_of_block(ord, blockIdx.x, tbx, tby)) return;
   x += blockIdx.z * zs;
   b += blockIdx.z * zs;
   xout += blockIdx.z * zs;
+  if (PRO) ec += blockIdx.z * zc;
   const int cx0 = tbx * TC, cy0 = tby * TC;
   const int x0 = (cx0 - 1) * K, y0 = (cy0 - 1) * K;  // residual tile origin (a vertex node)
   T* sX = pool;
@@ -462,6 +540,9 @@ __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, 
     }
   }
   T acc[G::NI][G::RW * K];
+  // x_in = x + P ec (the first post-smoothing step of a V-cycle level)
+  if (PRO)
+    prolong_into<T, S>(sX, pool + G::RY * G::RX, pool + G::RY * G::RX + S::CX * S::CX, sPT, ec, ptab, n1, x0, y0);
   __syncthreads();
   op_tile_any<T, G>(sX, sT, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
   // residual r = b - A x on the tile (0 on and outside the boundary)
@@ -538,7 +619,8 @@ template <> struct FusedTiles<7> { static constexpr int n = 2, tc[3] = {4, 2, 4}
 
 template <typename T, int K, int TC>
 hipError_t avs2d_tc(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout, T omega,
-                    hipStream_t s, int nsys, int64_t zs, const int* active) {
+                    hipStream_t s, int nsys, int64_t zs, const int* active, const T* ec, const T* ptab,
+                    int64_t zc) {
   using S = SmGeo<T, K, TC, 256>;
   const int n1 = K * N + 1;
   const int nt = (N + TC - 1) / TC;
@@ -548,19 +630,25 @@ hipError_t avs2d_tc(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T*
     return c.periodic && o >= c.left && o + (TC + 2) * K <= c.right0 && c0 >= 2 && c0 + TC <= N - 2;
   };
   const tile::TileOrder ord = tile::make_order(nt, nt, in, in);
-  avs2d_kernel<T, S><<<dim3(tile::order_blocks(ord), 1, nsys), S::NTH, 0, s>>>(
-      x, b, xout, N, n1, c.tab, c.nclass, c.left, c.right0, c.periodic, e.Q, e.lam, omega, zs, active, ord);
+  const dim3 grid(tile::order_blocks(ord), 1, nsys);
+  if (ec)
+    avs2d_kernel<T, S, true><<<grid, S::NTH, 0, s>>>(x, b, xout, N, n1, c.tab, c.nclass, c.left, c.right0,
+                                                     c.periodic, e.Q, e.lam, omega, zs, active, ord, ec, ptab, zc);
+  else
+    avs2d_kernel<T, S, false><<<grid, S::NTH, 0, s>>>(x, b, xout, N, n1, c.tab, c.nclass, c.left, c.right0,
+                                                      c.periodic, e.Q, e.lam, omega, zs, active, ord, ec, ptab, zc);
   return hipGetLastError();
 }
 
 template <typename T, int K>
 hipError_t avs2d_k(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout, T omega,
-                   hipStream_t s, int nsys, int64_t zs, const int* active, int variant) {
+                   hipStream_t s, int nsys, int64_t zs, const int* active, int variant, const T* ec, const T* ptab,
+                   int64_t zc) {
   using F = FusedTiles<K>;
   switch (variant < F::n ? variant : 0) {
-    case 1: return avs2d_tc<T, K, F::tc[1]>(N, c, e, x, b, xout, omega, s, nsys, zs, active);
-    case 2: return avs2d_tc<T, K, F::tc[2]>(N, c, e, x, b, xout, omega, s, nsys, zs, active);
-    default: return avs2d_tc<T, K, F::tc[0]>(N, c, e, x, b, xout, omega, s, nsys, zs, active);
+    case 1: return avs2d_tc<T, K, F::tc[1]>(N, c, e, x, b, xout, omega, s, nsys, zs, active, ec, ptab, zc);
+    case 2: return avs2d_tc<T, K, F::tc[2]>(N, c, e, x, b, xout, omega, s, nsys, zs, active, ec, ptab, zc);
+    default: return avs2d_tc<T, K, F::tc[0]>(N, c, e, x, b, xout, omega, s, nsys, zs, active, ec, ptab, zc);
   }
 }
 
@@ -576,8 +664,9 @@ hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, con
 
 template <typename T>
 hipError_t launch_avs2d(int k, int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* x, const T* b, T* xout,
-                        T omega, hipStream_t s, int nsys, int64_t zs, const int* active, int variant) {
-#define CALL(K) avs2d_k<T, K>(N, c, e, x, b, xout, omega, s, nsys, zs, active, variant)
+                        T omega, hipStream_t s, int nsys, int64_t zs, const int* active, int variant, const T* ec,
+                        const T* ptab, int64_t zc) {
+#define CALL(K) avs2d_k<T, K>(N, c, e, x, b, xout, omega, s, nsys, zs, active, variant, ec, ptab, zc)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
@@ -593,9 +682,11 @@ int avs2d_variants(int k) {
   }
 }
 template hipError_t launch_avs2d<double>(int, int, const LevelCoef<double>&, const LevelEig<double>&, const double*,
-                                         const double*, double*, double, hipStream_t, int, int64_t, const int*, int);
+                                         const double*, double*, double, hipStream_t, int, int64_t, const int*, int,
+                                         const double*, const double*, int64_t);
 template hipError_t launch_avs2d<float>(int, int, const LevelCoef<float>&, const LevelEig<float>&, const float*,
-                                        const float*, float*, float, hipStream_t, int, int64_t, const int*, int);
+                                        const float*, float*, float, hipStream_t, int, int64_t, const int*, int,
+                                        const float*, const float*, int64_t);
 template hipError_t launch_apply2d<double, double>(int, int, const LevelCoef<double>&, const double*,
                                                    const double*, double*, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_apply2d<float, double>(int, int, const LevelCoef<double>&, const float*,
