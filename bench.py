@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--cpu-N", type=int, default=128, help="cells per direction of the oracle sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-problem workload")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D Q3 128^3 kernel rates")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 2D degree sweep Q2..Q7")
     ap.add_argument("--only", default=None,
                     choices=["matvec_f64", "smoother_f64", "matvec_f32", "smoother_f32", "copy_f64"],
                     help="run only this kernel's timing loop (for counter collection) and print its ms")
@@ -174,6 +175,52 @@ def bench_3d(args, torch, P):
     return out
 
 
+# 2D degree sweep (Q2 512^2, Q3 512^2, Q4 512^2, Q5 256^2, Q6 256^2, Q7 256^2)
+SWEEP = [(2, 512), (3, 512), (4, 512), (5, 256), (6, 256), (7, 256)]
+
+
+def bench_sweep(args, torch, P):
+    """For each degree: FGMRES(50) to 1e-8 with the float32 V-cycle and with
+    the float64 V-cycle (iterations, seconds), and the float32-V-cycle
+    solution's relative distance to a float64-V-cycle solve driven to 1e-12
+    (the reference at sizes the oracle cannot factor)."""
+    from paper_2412_05082_amd.inputs import seeded_vector
+    dev = torch.device("cuda:0")
+    out = {"workload": "2D C0IP biharmonic degree sweep, seeded uniform[-1,1] RHS, omega 1/4, AVS 1+1", "runs": []}
+    for k, N in SWEEP:
+        b = torch.from_numpy(seeded_vector(2, k, N, 0)).to(dev)
+        row = {"degree": k, "cells": N, "dofs": b.numel()}
+        xs = {}
+        for name, dt in [("f32_vcycle", P.C0IP_F32), ("f64_vcycle", P.C0IP_F64)]:
+            pb = P.Problem(2, N, k, omega=args.omega, vcycle_dtype=dt)
+            pb.autotune()
+            x = torch.zeros_like(b)
+            pb.solve(b, x)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = pb.solve(b, x)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t0
+            row[name] = {"iterations": info["iterations"], "seconds": dt_s, "frac_iters": info["frac_iters"],
+                         "rel_res_true": info["rel_res_true"]}
+            xs[name] = x
+            if dt == P.C0IP_F64:
+                xr = torch.zeros_like(b)
+                pb.solve(b, xr, rtol=1e-12, max_iters=200, raise_on_nonconv=False)
+                torch.cuda.synchronize()
+                xs["ref"] = xr
+            pb.close()
+        ref = xs["ref"]
+        row["f32_vcycle"]["rel_err_vs_f64_1e-12"] = float(torch.linalg.norm(xs["f32_vcycle"] - ref) /
+                                                          torch.linalg.norm(ref))
+        row["f64_vcycle"]["rel_err_vs_f64_1e-12"] = float(torch.linalg.norm(xs["f64_vcycle"] - ref) /
+                                                          torch.linalg.norm(ref))
+        out["runs"].append(row)
+        del xs, ref, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def c5_problems():
     """Batched workload: 16 right-hand sides (seeds 0-15) on 2D Q4 256^2, plus
     48 problems i = 0..47 with N_i = 2^(3 + i mod 5) cells per direction,
@@ -269,6 +316,10 @@ def main():
               for _ in range(nsets)]
     ms_mv32 = time_kernel(lambda s: pmix.apply_A(s[0], s[1]), sets32, args.reps, torch)
     ms_smx32 = time_kernel(lambda s: pmix.smoother_step(s[2], s[0], s[1]), sets32, args.reps, torch)
+    # the atomic-scatter smoother step (residual pass, copy, patch solves with atomic adds), for comparison
+    pat = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F32, scatter_mode=1)
+    ms_at32 = time_kernel(lambda s: pat.smoother_step(s[2], s[0], s[1]), sets32, args.reps, torch)
+    pat.close()
     del sets32
     torch.cuda.empty_cache()
 
@@ -334,6 +385,8 @@ def main():
                            "alg_GBs": 8.0 * n / (ms_mv32 * 1e-3) / 1e9},
             "smoother_f32": {"ms": ms_smx32, "dofs_per_s": n / (ms_smx32 * 1e-3),
                              "alg_GBs": 12.0 * n / (ms_smx32 * 1e-3) / 1e9},
+            "smoother_f32_atomic_scatter": {"ms": ms_at32, "dofs_per_s": n / (ms_at32 * 1e-3),
+                                            "alg_GBs": 12.0 * n / (ms_at32 * 1e-3) / 1e9},
         },
         "tuned_tile_variant": {"f32": pmix.tuned_variant(dtype=P.C0IP_F32),
                                "f64": p64.tuned_variant(dtype=P.C0IP_F64)},
@@ -345,6 +398,8 @@ def main():
     }
     if not args.no_batch:
         out["config_batched"] = bench_batch(torch, P)
+    if not args.no_sweep:
+        out["config_degree_sweep"] = bench_sweep(args, torch, P)
     if not args.no_3d:
         del pmix, p64
         torch.cuda.empty_cache()

@@ -69,8 +69,14 @@ typedef struct {
  *   solve is always float64).
  * coarse_mode: 0 = exact level-0 solve (float64 dense inverse from a
  *   Cholesky factorisation); 1 = one smoothing step with omega = 1.
- * scatter_mode: 0 = owner-computes tiles (deterministic, no atomics); other
- *   values are rejected with C0IP_EUNSUPPORTED.
+ * scatter_mode: how a smoothing step adds the overlapping patch corrections
+ *   (Sec. 3; the paper compares coloured and atomic scatters).  0 = owner
+ *   computes: each tile solves every patch touching it and writes each of
+ *   its DoFs once (deterministic, no atomics).  1 = atomic: each patch is
+ *   solved once and its correction added with floating-point atomics
+ *   (results agree to rounding, not bit for bit; 2D only, else
+ *   C0IP_EUNSUPPORTED; batched solves accept 0 only).  Other values:
+ *   C0IP_EINVAL.
  * tail_levels: in 2D with degree <= 4, the lowest levels of the V-cycle can
  *   run as one launch of a single workgroup per system, all their vectors
  *   in LDS (same operations, fewer launches).  -1 = as many levels as fit

@@ -207,13 +207,13 @@ class Batch:
     """Owns a c0ip_batch: problems = [(n_cells, degree), ...] (2D), n_rhs per problem."""
 
     def __init__(self, problems, n_rhs, gamma=0.0, omega=0.25, pre_steps=1, post_steps=1, vcycle_dtype=C0IP_F32,
-                 coarse_mode=0, tail_levels=-1, stream=None):
+                 coarse_mode=0, tail_levels=-1, scatter_mode=0, stream=None):
         lib = load_library()
         self.problems = list(problems)
         self.n_rhs = list(n_rhs)
         meshes = (MeshDesc * len(self.problems))(*[MeshDesc(2, N, k, gamma) for N, k in self.problems])
         rhs = (C.c_int * len(self.n_rhs))(*self.n_rhs)
-        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, 0, tail_levels)
+        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

@@ -179,6 +179,18 @@ void c0ip_problem::smooth(int l, const T* b, T* x, int steps, bool x_is_zero) {
     if (x_is_zero) check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), x, stream), "fill");
     return;
   }
+  if (mg.scatter_mode == 1) {  // atomic scatter: in place, residual through the level's r
+    for (int s = 0; s < steps; ++s) {
+      if (s == 0 && x_is_zero) {
+        check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), x, stream), "fill");
+        check(c0ip::launch_patch2d_atomic<T>(k, Nl, w.eig, b, x, om, stream), "atomic smoother");
+      } else {
+        check(c0ip::launch_apply2d<T, T>(k, Nl, w.coef, x, b, w.r.p, stream), "residual");
+        check(c0ip::launch_patch2d_atomic<T>(k, Nl, w.eig, w.r.p, x, om, stream), "atomic smoother");
+      }
+    }
+    return;
+  }
   int s0 = 0;
   if (x_is_zero) {
     check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, b, nullptr, x, om, stream), "smoother");
@@ -194,6 +206,11 @@ void c0ip_problem::smooth_from(int l, const T* b, T* from, T* x, int steps) {
   LevelWork<T>& w = work<T>(l);
   const int Nl = lv[l]->N;
   const T om = (T)mg.omega;
+  if (mg.scatter_mode == 1) {
+    if (from != x) check(hipMemcpyAsync(x, from, sizeof(T) * lv[l]->ntot, hipMemcpyDeviceToDevice, stream), "copy");
+    smooth<T>(l, b, x, steps, false);
+    return;
+  }
   if (dim == 2) {
     T* cur = from;
     T* oth = (from == x) ? w.r.p : x;
@@ -221,7 +238,7 @@ int c0ip_problem::tail_level() {
   int& t = tailLT[sizeof(T) == 4 ? 1 : 0];
   if (t != -2) return t;
   t = -1;
-  if (dim != 2 || k > 4 || mg.tail_levels == 0) return t;
+  if (dim != 2 || k > 4 || mg.tail_levels == 0 || mg.scatter_mode != 0) return t;
   const int lim = c0ip::tail_lds_limit();
   int cap = std::min(L, c0ip::kTailMaxLevels - 1);
   if (mg.tail_levels > 0) cap = std::min(cap, mg.tail_levels - 1);
@@ -334,7 +351,7 @@ void c0ip_problem::mg_level(int l, const T* b, T* x) {
   }
   LevelWork<T>& w = work<T>(l);
   LevelWork<T>& wc = work<T>(l - 1);
-  if (dim == 2) {
+  if (dim == 2 && mg.scatter_mode == 0) {
     mg_level2d<T>(l, b, x);
     return;
   }
@@ -434,7 +451,9 @@ c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, vo
     return fail(C0IP_EINVAL, "smoothing steps must be in [0,16]");
   if (mg.vcycle_dtype != C0IP_F64 && mg.vcycle_dtype != C0IP_F32) return fail(C0IP_EINVAL, "bad vcycle_dtype");
   if (mg.coarse_mode != 0 && mg.coarse_mode != 1) return fail(C0IP_EINVAL, "coarse_mode must be 0 or 1");
-  if (mg.scatter_mode != 0) return fail(C0IP_EUNSUPPORTED, "only scatter_mode 0 (owner-computes) is built");
+  if (mg.scatter_mode != 0 && mg.scatter_mode != 1) return fail(C0IP_EINVAL, "scatter_mode must be 0 or 1");
+  if (mg.scatter_mode == 1 && mesh->dim != 2)
+    return fail(C0IP_EUNSUPPORTED, "the atomic-scatter smoother is built for 2D meshes only");
   if (mg.tail_levels < -1) return fail(C0IP_EINVAL, "tail_levels must be >= -1");
   std::unique_ptr<c0ip_problem> p(new c0ip_problem());
   p->dim = mesh->dim;
@@ -589,7 +608,16 @@ c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, con
       const T* bb = (const T*)b;
       const T* xi = (const T*)x_in;
       T* xo = (T*)x_out;
-      if (!xi) {
+      if (p->mg.scatter_mode == 1) {
+        if (xi) {
+          p->check(c0ip::launch_apply2d<T, T>(p->k, Nl, w.coef, xi, bb, w.r.p, p->stream), "residual");
+          p->check(hipMemcpyAsync(xo, xi, sizeof(T) * p->lv[l]->ntot, hipMemcpyDeviceToDevice, p->stream), "copy");
+        } else {
+          p->check(c0ip::launch_fill_t<T>(p->lv[l]->ntot, T(0), xo, p->stream), "fill");
+        }
+        p->check(c0ip::launch_patch2d_atomic<T>(p->k, Nl, w.eig, xi ? w.r.p : bb, xo, om, p->stream),
+                 "atomic smoother");
+      } else if (!xi) {
         p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, bb, nullptr, xo, om, p->stream), "smoother");
       } else if (p->dim == 2) {
         p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, xi, bb, xo, om, p->stream, 1, 0, nullptr,

@@ -92,6 +92,10 @@ hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, con
 template <typename T>
 hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
                           hipStream_t s, int nsys = 1, int64_t zs = 0, const int* active = nullptr);
+// xout += omega * sum_v R_v^T A~_v^{-1} R_v r with floating-point atomics
+// (xout initialised by the caller; each patch solved once).
+template <typename T>
+hipError_t launch_patch2d_atomic(int k, int N, const LevelEig<T>& e, const T* r, T* xout, T omega, hipStream_t s);
 // One fused smoothing step S(x, b) (residual in LDS; x_out must not alias x).
 // variant: tile-size variant (0 = default; see avs2d_variants).  With ec:
 // the step starts from x + P ec instead (ec: coarse vector of the level

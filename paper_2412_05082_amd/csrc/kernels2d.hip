@@ -176,6 +176,107 @@ hipError_t patch2d_k(int N, const LevelEig<T>& e, const T* r, const T* xin, T* x
   return hipGetLastError();
 }
 
+// Atomic-scatter form of the smoother step (the comparison variant): a
+// workgroup solves TC x TC patches, each exactly once (no redundant border
+// patches), and adds omega times every patch correction into x_out with
+// hardware floating-point atomics.  The caller initialises x_out (x_in or
+// 0); the summation order of overlapping patches is not fixed, so results
+// agree with the owner-computes kernels to rounding, not bit for bit.
+template <typename T, int K, int TC>
+__global__ __launch_bounds__(kThreads) void patch2d_atomic_kernel(const T* __restrict__ r, T* __restrict__ xout,
+                                                                  int N, int n1, const T* __restrict__ Qg,
+                                                                  const T* __restrict__ lamg, T omega) {
+  constexpr int n = 2 * K - 1, NN = n * n, NP = TC, S = (TC + 1) * K - 1;
+  __shared__ T sR[S * S];
+  __shared__ T sA[NP * NP * NN];
+  __shared__ T sB[NP * NP * NN];
+  __shared__ T sQ[4 * NN];
+  __shared__ T sLam[4 * n];
+  int tbx, tby;
+  xcd_tile(tbx, tby);
+  const int vx0 = tbx * TC + 1, vy0 = tby * TC + 1;  // first vertex of the block
+  const int ox = (vx0 - 1) * K + 1, oy = (vy0 - 1) * K + 1;
+  for (int e = threadIdx.x; e < S * S; e += kThreads) {
+    const int rr = e / S, cc = e - rr * S;
+    const int gy = oy + rr, gx = ox + cc;
+    sR[e] = (gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2) ? r[(size_t)gy * n1 + gx] : T(0);
+  }
+  for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
+  for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
+  __syncthreads();
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, a = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = vx0 + pxl, vy = vy0 + pyl;
+    if (vx > N - 1 || vy > N - 1) continue;
+    const T* q = sQ + variant(vx, N) * NN;
+    T in[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) in[c] = sR[(pyl * K + a) * S + pxl * K + c];
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int cp = 0; cp < n; ++cp) s += q[cp * n + c] * in[cp];
+      sA[p * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, c = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = vx0 + pxl, vy = vy0 + pyl;
+    if (vx > N - 1 || vy > N - 1) continue;
+    const int ty = variant(vy, N), tx = variant(vx, N);
+    const T* q = sQ + ty * NN;
+    T col[n], t[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) col[a] = sA[p * NN + a * n + c];
+#pragma unroll
+    for (int ap = 0; ap < n; ++ap) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) s += q[a * n + ap] * col[a];
+      t[ap] = s / (sLam[tx * n + c] + sLam[ty * n + ap]);
+    }
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int ap = 0; ap < n; ++ap) s += q[a * n + ap] * t[ap];
+      sB[p * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < NP * NP * n; it += kThreads) {
+    const int p = it / n, a = it - p * n;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = vx0 + pxl, vy = vy0 + pyl;
+    if (vx > N - 1 || vy > N - 1) continue;
+    const T* q = sQ + variant(vx, N) * NN;
+    T in[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) in[c] = sB[p * NN + a * n + c];
+    const int gy = (vy - 1) * K + 1 + a, gx0 = (vx - 1) * K + 1;
+#pragma unroll
+    for (int cp = 0; cp < n; ++cp) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < n; ++c) s += q[cp * n + c] * in[c];
+      unsafeAtomicAdd(xout + (size_t)gy * n1 + gx0 + cp, omega * s);
+    }
+  }
+}
+
+template <typename T, int K>
+hipError_t patch2d_atomic_k(int N, const LevelEig<T>& e, const T* r, T* xout, T omega, hipStream_t s) {
+  constexpr int TC = PatchTile2D<K>::TC;
+  const int n1 = K * N + 1;
+  const int nt = (N - 1 + TC - 1) / TC;
+  patch2d_atomic_kernel<T, K, TC><<<dim3(nt, nt), kThreads, 0, s>>>(r, xout, N, n1, e.Q, e.lam, omega);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ transfers
 // Restriction b_c = P^T r_f and prolongation x_f += P e_c in one launch each:
 // a workgroup owns TCC x TCC coarse cells, stages its fine (or coarse)
@@ -343,6 +444,13 @@ hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const 
 }
 
 template <typename T>
+hipError_t launch_patch2d_atomic(int k, int N, const LevelEig<T>& e, const T* r, T* xout, T omega, hipStream_t s) {
+#define CALL(K) patch2d_atomic_k<T, K>(N, e, r, xout, omega, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template <typename T>
 hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s, int nsys,
                              int64_t zf, int64_t zc, const int* active) {
 #define CALL(K) restrict2d_k<T, K>(Nc, table, rf, bc, s, nsys, zf, zc, active)
@@ -366,6 +474,10 @@ template hipError_t launch_prolong2d<double>(int, int, const double*, const doub
                                              hipStream_t, int, int64_t, int64_t, const int*);
 template hipError_t launch_prolong2d<float>(int, int, const float*, const float*, const float*, float*, hipStream_t,
                                             int, int64_t, int64_t, const int*);
+template hipError_t launch_patch2d_atomic<double>(int, int, const LevelEig<double>&, const double*, double*,
+                                                  double, hipStream_t);
+template hipError_t launch_patch2d_atomic<float>(int, int, const LevelEig<float>&, const float*, float*, float,
+                                                 hipStream_t);
 template hipError_t launch_patch2d<double>(int, int, const LevelEig<double>&, const double*, const double*,
                                            double*, double, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_patch2d<float>(int, int, const LevelEig<float>&, const float*, const float*, float*,

@@ -224,7 +224,10 @@ def test_abi_rejects_bad_arguments():
         P.Problem(2, 8, 3, omega=-1.0)
     assert e.value.status == -1
     with pytest.raises(P.C0ipError) as e:
-        P.Problem(2, 8, 3, scatter_mode=1)
+        P.Problem(2, 8, 3, scatter_mode=2)
+    assert e.value.status == -1
+    with pytest.raises(P.C0ipError) as e:
+        P.Problem(3, 4, 3, scatter_mode=1)
     assert e.value.status == -6
     pb = P.Problem(2, 8, 3)
     with pytest.raises(ValueError):
