@@ -114,6 +114,9 @@ hipError_t launch_prolong2d(int k, int Nc, const T* table, const T* ec, const T*
                             int nsys = 1, int64_t zc = 0, int64_t zf = 0, const int* active = nullptr);
 template <typename Tin, typename T>
 hipError_t launch_apply3d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s);
+// z-streaming operator with per-lane band loops (any k; used for k >= 5).
+template <typename Tin, typename T>
+hipError_t launch_apply3d_wide(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s);
 template <typename T>
 hipError_t launch_patch3d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
                           hipStream_t s);

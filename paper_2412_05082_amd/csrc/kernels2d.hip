@@ -10,7 +10,7 @@
 #include <algorithm>
 
 #include "kernels.h"
-#include "tile2d.h"
+#include "tiles.h"
 
 namespace c0ip {
 namespace {

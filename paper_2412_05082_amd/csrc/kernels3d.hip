@@ -326,7 +326,7 @@ hipError_t patch3d_k(int N, const LevelEig<T>& e, const T* r, const T* xin, T* x
 }  // namespace
 
 template <typename Tin, typename T>
-hipError_t launch_apply3d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s) {
+hipError_t launch_apply3d_wide(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s) {
 #define CALL(K) apply3d_k<Tin, T, K>(N, c, x, b, y, s)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
@@ -340,11 +340,11 @@ hipError_t launch_patch3d(int k, int N, const LevelEig<T>& e, const T* r, const 
 #undef CALL
 }
 
-template hipError_t launch_apply3d<double, double>(int, int, const LevelCoef<double>&, const double*,
+template hipError_t launch_apply3d_wide<double, double>(int, int, const LevelCoef<double>&, const double*,
                                                    const double*, double*, hipStream_t);
-template hipError_t launch_apply3d<float, double>(int, int, const LevelCoef<double>&, const float*,
+template hipError_t launch_apply3d_wide<float, double>(int, int, const LevelCoef<double>&, const float*,
                                                   const double*, double*, hipStream_t);
-template hipError_t launch_apply3d<float, float>(int, int, const LevelCoef<float>&, const float*, const float*,
+template hipError_t launch_apply3d_wide<float, float>(int, int, const LevelCoef<float>&, const float*, const float*,
                                                  float*, hipStream_t);
 template hipError_t launch_patch3d<double>(int, int, const LevelEig<double>&, const double*, const double*,
                                            double*, double, hipStream_t);

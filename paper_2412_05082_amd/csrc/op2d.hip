@@ -19,12 +19,14 @@
 #include <algorithm>
 
 #include "kernels.h"
-#include "tile2d.h"
+#include "tiles.h"
 
 namespace c0ip {
 namespace {
 
 using tile::Band;
+using tile::band_row;
+using tile::clampi;
 
 // Cell positions [p0, end) whose bands of factor OP fit the scalar budget
 // (80 SGPRs of coefficients).
@@ -36,7 +38,6 @@ constexpr int group_end(int p0) {
   return p == p0 ? p0 + 1 : p;
 }
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Tile geometry: TXC x TYC cells, NTH threads, x items of CW cells, y items
 // of RW cell rows.
@@ -48,36 +49,6 @@ struct Geo {
   static constexpr int TABMAX = 3 * (5 * K + 2) * W;  // row classes: at most 5k+2
   static_assert(TXC % CW == 0 && TYC % RW == 0, "item sizes must divide the tile");
 };
-
-// Band product of factor OP for the row at cell position p with
-// coefficients c (centred) and inputs v (v[0] = the band's first tap).
-template <typename T, int OP, int K>
-__device__ __forceinline__ T band_dot(const T* __restrict__ c, const T* v, int p) {
-  T a = 0;
-#pragma unroll
-  for (int o = Band<OP, K>::lo(p); o <= Band<OP, K>::hi(p); ++o) a += c[o] * v[o];
-  return a;
-}
-
-// Rows of the periodic classes share one coefficient row per cell
-// position, read with wave-uniform addresses from the global table.  On
-// interior tiles (UNIFORM) every row is periodic.  Elsewhere the few lanes
-// whose row is in a boundary class (or every lane on meshes too small to
-// have periodic rows) redo the product with their own row from the
-// workgroup's LDS copy of the table.
-template <typename T, int OP, int K, bool UNIFORM>
-__device__ __forceinline__ T band_row(const T* __restrict__ tab, const T* __restrict__ sTab, int nclass, int left,
-                                      int periodic, int cl, const T* v, int p) {
-  constexpr int W = 4 * K + 1, H = 2 * K;
-  if constexpr (UNIFORM) {
-    return band_dot<T, OP, K>(tab + (size_t)(OP * nclass + 2 * left + p) * W + H, v, p);
-  } else {
-    T a = 0;
-    if (periodic) a = band_dot<T, OP, K>(tab + (size_t)(OP * nclass + 2 * left + p) * W + H, v, p);
-    if (!periodic || cl != 2 * left + p) a = band_dot<T, OP, K>(sTab + (OP * nclass + cl) * W + H, v, p);
-    return a;
-  }
-}
 
 // T[r][.] = X[r][.] op_x for rows [r0, r1) and cell positions [P0, P1).
 template <typename T, class G, int OP, int P0, int P1, bool XIN>

@@ -1,5 +1,5 @@
-// Device helpers shared by the 2D tile kernels (row classes of the 1D
-// factors, structural bands, XCD-aware tile order).
+// Device helpers shared by the tile kernels (row classes of the 1D
+// factors, structural bands and band products, XCD-aware tile order).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -77,7 +77,7 @@ inline TileOrder make_order(int tx, int ty, FX xin, FY yin) {
   o.nbp = (o.nb + 7) & ~7;
   return o;
 }
-inline int order_blocks(const TileOrder& o) {
+__host__ __device__ inline int order_blocks(const TileOrder& o) {
   return o.nbp + (o.bx_hi - o.bx_lo + 1) * (o.by_hi - o.by_lo + 1);
 }
 
@@ -131,6 +131,38 @@ struct Band {
   static constexpr int win_lo(int p0) { return 2 * K + (p0 == 0 ? lo(0) : lo(1) + 1); }
   static constexpr int win_hi() { return 2 * K + (OP == 2 ? 2 * K : K); }
 };
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Band product of factor OP for the row at cell position p with
+// coefficients c (centred) and inputs v (v[0] = the band's first tap).
+template <typename T, int OP, int K>
+__device__ __forceinline__ T band_dot(const T* __restrict__ c, const T* v, int p) {
+  T a = 0;
+#pragma unroll
+  for (int o = Band<OP, K>::lo(p); o <= Band<OP, K>::hi(p); ++o) a += c[o] * v[o];
+  return a;
+}
+
+// Rows of the periodic classes share one coefficient row per cell
+// position, read with wave-uniform addresses from the global table.  On
+// interior tiles (UNIFORM) every row is periodic.  Elsewhere the few lanes
+// whose row is in a boundary class (or every lane on meshes too small to
+// have periodic rows) redo the product with their own row from the
+// workgroup's LDS copy of the table.
+template <typename T, int OP, int K, bool UNIFORM>
+__device__ __forceinline__ T band_row(const T* __restrict__ tab, const T* __restrict__ sTab, int nclass, int left,
+                                      int periodic, int cl, const T* v, int p) {
+  constexpr int W = 4 * K + 1, H = 2 * K;
+  if constexpr (UNIFORM) {
+    return band_dot<T, OP, K>(tab + (size_t)(OP * nclass + 2 * left + p) * W + H, v, p);
+  } else {
+    T a = 0;
+    if (periodic) a = band_dot<T, OP, K>(tab + (size_t)(OP * nclass + 2 * left + p) * W + H, v, p);
+    if (!periodic || cl != 2 * left + p) a = band_dot<T, OP, K>(sTab + (OP * nclass + cl) * W + H, v, p);
+    return a;
+  }
+}
 
 }  // namespace tile
 }  // namespace c0ip

@@ -31,6 +31,60 @@ def test_apply_A_3d(dim, k, N):
     assert rel_l2(host(y32), A @ x32.astype(np.float64)) <= 1e-5
 
 
+def test_apply_A_3d_k2_n16_full():
+    """k = 2, 16^3 cells: two y tiles and two z chunks of the operator kernel,
+    every output against the assembled matrix."""
+    dim, k, N = 3, 2, 16
+    say("3d apply_A full", dim, k, N)
+    A = O.assemble(dim, k, N)
+    x, _ = vectors(dim, k, N)
+    pb = P.Problem(dim, N, k)
+    y = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    pb.apply_A(dev(x), y)
+    torch.cuda.synchronize()
+    assert rel_l2(host(y), A @ x) <= 1e-12
+
+
+def _tile_seam_nodes(k, N, rng, count):
+    """Nodes next to the seams of the operator's tiles and z chunks (cells
+    multiple of 4 and 16 in x, y and z), next to the boundary, and random."""
+    n1 = k * N + 1
+    seams = sorted({c * k + d for c in range(0, N + 1, 4) for d in (-1, 0, 1)} & set(range(n1)))
+    pick = [(int(rng.choice(seams)), int(rng.choice(seams)), int(rng.choice(seams))) for _ in range(count)]
+    pick += [(1, 1, 1), (n1 - 2, n1 - 2, n1 - 2), (0, 5, 5), (n1 - 1, 3, 4), (2, n1 - 1, n1 - 1)]
+    return np.array([i + n1 * (j + n1 * l) for i, j, l in pick])
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_apply_A_3d_n32_sampled(k):
+    """32^3 cells: several x and y tiles, ragged tiles and several z chunks;
+    A x (float64 and float32) and one smoothing step at nodes on the seams."""
+    dim, N = 3, 32
+    say("3d apply_A sampled", dim, k, N)
+    x, b = vectors(dim, k, N)
+    pb = P.Problem(dim, N, k, omega=0.1)
+    y = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    pb.apply_A(dev(x), y)
+    x32 = x.astype(np.float32)
+    y32 = torch.empty(x.size, dtype=torch.float32, device="cuda")
+    pb.apply_A(dev(x32), y32)
+    xs = dev(x)
+    pb.apply_smoother(dev(b), xs)
+    torch.cuda.synchronize()
+    yh, y32h, sh = host(y), host(y32), host(xs)
+    rng = np.random.default_rng(11)
+    nodes = _tile_seam_nodes(k, N, rng, 24)
+    ya = O.apply_rows_windowed(dim, k, N, x, nodes)
+    scale = np.abs(ya).max()
+    assert np.abs(yh[nodes] - ya).max() <= 1e-12 * scale
+    ya32 = O.apply_rows_windowed(dim, k, N, x32.astype(np.float64), nodes)
+    assert np.abs(y32h[nodes] - ya32).max() <= 1e-5 * scale
+    sn = nodes[: {2: 4, 3: 2, 4: 1}[k]]
+    sa = O.avs_nodes_windowed(dim, k, N, x, b, 0.1, sn)
+    assert np.abs(sh[sn] - sa).max() <= fp64_tol(dim, k, 8) * np.abs(sa).max()
+    assert np.isfinite(yh).all() and np.isfinite(y32h).all() and np.isfinite(sh).all()
+
+
 @pytest.mark.parametrize("dim,k,N", SMALL3)
 @pytest.mark.parametrize("x_is_zero", [False, True])
 def test_smoother_3d(dim, k, N, x_is_zero):
