@@ -1,5 +1,5 @@
 """Build libc0ip.so in-tree for gfx950 (hipcc for the HIP sources, g++ for
-the host set-up).  Usage: ``python -m paper_2412_05082_amd.build``."""
+the host set-up and for the generator of the reference-coefficient header).  Usage: ``python -m paper_2412_05082_amd.build``."""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -20,7 +20,7 @@ ARCH = os.environ.get("C0IP_OFFLOAD_ARCH", "gfx950")
 # packed FP32 instructions are kept out of every code object
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-command-line-argument", f"-I{INCLUDE}", f"-I{CSRC}"]
+             "-Wno-unused-command-line-argument", f"-I{INCLUDE}", f"-I{CSRC}", f"-I{BUILD}"]
 
 
 def _hipcc():
@@ -40,6 +40,11 @@ def _run(cmd):
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
+    # generated header: reference 1D coefficient rows (compile-time constants of the 3D operator)
+    gen = os.path.join(BUILD, "gen_refcoef")
+    _run(["g++", "-O2", "-std=c++17", f"-I{CSRC}", os.path.join(CSRC, "gen_refcoef.cpp"),
+          os.path.join(CSRC, "setup.cpp"), "-o", gen])
+    _run([gen, os.path.join(BUILD, "refcoef.h")])
     cmds = []
     objs = []
     for s in HIP_SOURCES:

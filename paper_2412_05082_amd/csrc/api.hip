@@ -66,6 +66,7 @@ std::vector<T> cast_vec(const std::vector<double>& v) {
 template <typename T>
 struct LevelWork {
   DevBuf<T> tab, Q, lam, ptab;  // coefficient table, eigenbases, prolongation table
+  DevBuf<T> tabref;             // the table scaled to h = 1 (default penalty only)
   DevBuf<T> x, b, r, scratch;   // V-cycle vectors and transfer scratch
   DevBuf<T> t;                  // 2D: second iterate buffer (smoothing steps are out of place)
   c0ip::LevelCoef<T> coef;
@@ -153,6 +154,16 @@ void c0ip_problem::prepare(int l) {
   w.coef.left = L_.rc.left;
   w.coef.right0 = L_.rc.right0;
   w.coef.periodic = L_.rc.periodic;
+  if (gamma == (double)(k * (k + 1))) {
+    // M = h M^, L = L^ / h, B = B^ / h^3 on a uniform mesh
+    const double h = L_.lv.h, sc[3] = {1.0 / h, h, h * h * h};
+    std::vector<double> r(L_.tab);
+    const size_t per = r.size() / 3;
+    for (size_t i = 0; i < r.size(); ++i) r[i] *= sc[i / per];
+    w.tabref.upload(cast_vec<T>(r));
+    w.coef.ref = w.tabref.p;
+    w.coef.hinv = (T)(1.0 / h);
+  }
   w.eig.Q = w.Q.p;
   w.eig.lam = w.lam.p;
   w.x.alloc(L_.ntot);

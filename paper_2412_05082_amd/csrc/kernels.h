@@ -12,6 +12,11 @@ template <typename T>
 struct LevelCoef {
   const T* tab = nullptr;  // [3][nclass][4k+1]
   int nclass = 0, left = 0, right0 = 0, periodic = 0;
+  // With the default penalty: the same table scaled to h = 1 (M / h, L h,
+  // B h^3), whose periodic rows are the compile-time reference rows, and
+  // 1/h; ref == nullptr otherwise.
+  const T* ref = nullptr;
+  T hinv = 0;
 };
 
 // Fast-diagonalisation data of one level: Q[4][n*n], lam[4][n].

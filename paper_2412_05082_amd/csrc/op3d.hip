@@ -22,17 +22,22 @@
 //     register window of the 4k+1 output planes it reaches; the oldest
 //     cell of the window is complete after the first plane of each cell
 //     and is written out.
-// The row class of a plane is the same for the whole workgroup, so the z
-// coefficients are read with wave-uniform addresses on every plane; the x
-// and y coefficients are wave-uniform on tiles whose rows are all in the
-// periodic classes, and come per lane from an LDS copy of the table on the
-// others.  Output nodes on the faces x, y or z = 1 (the last node) are
+// Coefficients: with the default penalty the rows of the periodic classes
+// are h-scaled copies of reference rows (h = 1) that are compile-time
+// constants (generated at build time by gen_refcoef.cpp); every term of the
+// 3D operator then carries the same factor 1/h, applied to the output.  On
+// tiles whose x (y) rows are all periodic the x (y) coefficients are these
+// constants; elsewhere the lanes in boundary classes redo their product with
+// their own row from an LDS copy of the reference-scaled table.  The row
+// class of a plane is the same for the whole workgroup: the z rows are read
+// with wave-uniform addresses.  Output nodes on the faces x, y or z = 1 (the last node) are
 // boundary nodes (zero rows of every 1D factor): tiles cover nodes
 // [0, kN), and extra workgroups write those faces as zeros.
 #include <algorithm>
 #include <type_traits>
 
 #include "kernels.h"
+#include "refcoef.h"
 #include "tiles.h"
 
 namespace c0ip {
@@ -41,10 +46,10 @@ namespace {
 using tile::Band;
 using tile::clampi;
 
-// The coefficient loads of a plane are loop invariant on interior tiles;
-// hoisted out of the plane loop, they and their addresses would not fit the
-// scalar registers.  Passing a row offset through an empty asm statement
-// on a scalar register, inside the loop, keeps them next to their use.
+// The coefficient loads of a boundary plane are loop invariant; hoisted
+// out of the plane loop they would not fit the scalar registers.  Passing
+// the row offset through an empty asm statement on a scalar register keeps
+// them inside.
 __device__ __forceinline__ int opaque(int v) {
   asm volatile("" : "+s"(v));
   return v;
@@ -58,43 +63,41 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// Cell positions [p0, end) whose bands of factor OP take at most 48 scalar
-// registers of coefficients.
-template <typename T, int OP, int K>
-constexpr int pgroup_end(int p0) {
-  constexpr int budget = 48 / (int)(sizeof(T) / 4);
-  int s = 0, p = p0;
-  while (p < K && s + Band<OP, K>::width(p) <= budget) s += Band<OP, K>::width(p++);
-  return p == p0 ? p0 + 1 : p;
+// Reference row of factor OP (0 = M, 1 = L, 2 = B) at cell position p.
+template <int K, int OP>
+__device__ __forceinline__ constexpr double ref_coef(int p, int j) {
+  if constexpr (OP == 0)
+    return RefCoef<K>::m[p][j];
+  else if constexpr (OP == 1)
+    return RefCoef<K>::l[p][j];
+  else
+    return RefCoef<K>::b[p][j];
 }
 
-// f(tp, p) for the cell positions p of factor OP, one group of positions
-// at a time; tp is the coefficient row (centred) of the periodic class at
-// cell position 0, formed anew for each group so that the group's loads
-// stay next to their use.
-template <typename T, int OP, int K, int P0, class F>
-__device__ __forceinline__ void for_pgroups(const T* __restrict__ tab, int nclass, int left, F&& f) {
-  constexpr int P1 = pgroup_end<T, OP, K>(P0);
-  __builtin_amdgcn_sched_barrier(0);
-  const T* tp = tab + opaque((OP * nclass + 2 * left) * (4 * K + 1) + 2 * K);
-  static_for<P0, P1>([&](auto pc) { f(tp, pc); });
-  if constexpr (P1 < K) for_pgroups<T, OP, K, P1>(tab, nclass, left, f);
+// Band product with the reference row (constants) of the periodic class at
+// cell position p; v centred on the row.
+template <typename T, int OP, int K>
+__device__ __forceinline__ T band_ref(const T* v, int p) {
+  T a = 0;
+#pragma unroll
+  for (int o = Band<OP, K>::lo(p); o <= Band<OP, K>::hi(p); ++o) a += (T)ref_coef<K, OP>(p, 2 * K + o) * v[o];
+  return a;
 }
 
 // Band product of factor OP for the row at cell position p of class cl:
-// the periodic row at tp + p W on tiles whose rows are all periodic
-// (UNIFORM); elsewhere the lanes in boundary classes (every lane on meshes
-// without periodic rows) redo it with their own row from the LDS copy of
-// the table.
+// the reference row on tiles whose rows are all periodic (UNIFORM);
+// elsewhere the lanes in boundary classes (every lane on meshes without
+// periodic rows) redo it with their own row of the reference-scaled table
+// in LDS.
 template <typename T, int OP, int K, bool UNIFORM>
-__device__ __forceinline__ T band3(const T* __restrict__ tp, const T* __restrict__ sTab, int nclass, int left,
-                                   int periodic, int cl, const T* v, int p) {
+__device__ __forceinline__ T band3(const T* __restrict__ sTab, int nclass, int left, int periodic, int cl,
+                                   const T* v, int p) {
   constexpr int W = 4 * K + 1, H = 2 * K;
   if constexpr (UNIFORM) {
-    return tile::band_dot<T, OP, K>(tp + p * W, v, p);
+    return band_ref<T, OP, K>(v, p);
   } else {
     T a = 0;
-    if (periodic) a = tile::band_dot<T, OP, K>(tp + p * W, v, p);
+    if (periodic) a = band_ref<T, OP, K>(v, p);
     if (!periodic || cl != 2 * left + p) a = tile::band_dot<T, OP, K>(sTab + (OP * nclass + cl) * W + H, v, p);
     return a;
   }
@@ -120,8 +123,8 @@ struct Geo3 {
 // (row r, group g of CW cells), rows fastest across lanes.
 template <typename T, class G, bool XIN>
 __device__ __forceinline__ void xpass3(const T* __restrict__ sX, T* __restrict__ sTM, T* __restrict__ sTL,
-                                       T* __restrict__ sTB, const T* __restrict__ tab, const T* __restrict__ sTab,
-                                       int nclass, int left, int right0, int periodic, int x0, int n1) {
+                                       T* __restrict__ sTB, const T* __restrict__ sTab, int nclass, int left,
+                                       int right0, int periodic, int x0, int n1) {
   constexpr int K = G::K, CW = G::CW, H = G::H, TX = G::TX;
   constexpr int LO = Band<2, K>::win_lo(0), HI = Band<2, K>::win_hi() + (CW - 1) * K;
   for (int it = threadIdx.x; it < G::NXI; it += G::NTH) {
@@ -134,14 +137,13 @@ __device__ __forceinline__ void xpass3(const T* __restrict__ sX, T* __restrict__
     };
     auto pass = [&](auto opc, T* __restrict__ out) {
       constexpr int OP = decltype(opc)::value;
-      for_pgroups<T, OP, K, 0>(tab, nclass, left, [&](const T* tp, auto pc) {
-        constexpr int p = decltype(pc)::value;
+#pragma unroll
+      for (int p = 0; p < K; ++p)
 #pragma unroll
         for (int w = 0; w < CW; ++w) {
           const int col = (g * CW + w) * K + p;
-          out[col] = band3<T, OP, K, XIN>(tp, sTab, nclass, left, periodic, cls(col, p), in + (w * K + p + H - LO), p);
+          out[col] = band3<T, OP, K, XIN>(sTab, nclass, left, periodic, cls(col, p), in + (w * K + p + H - LO), p);
         }
-      });
     };
     pass(std::integral_constant<int, 0>{}, sTM + r * G::TXP);
     if (r >= K && r < G::RY - K) {
@@ -157,8 +159,8 @@ __device__ __forceinline__ void xpass3(const T* __restrict__ sX, T* __restrict__
 template <typename T, class G, bool YIN>
 __device__ __forceinline__ void ypass3(const T* __restrict__ sTM, const T* __restrict__ sTL,
                                        const T* __restrict__ sTB, T (&S1)[G::K], T (&S2)[G::K], T (&S3)[G::K],
-                                       const T* __restrict__ tab, const T* __restrict__ sTab, int nclass, int left,
-                                       int right0, int periodic, int y0, int n1) {
+                                       const T* __restrict__ sTab, int nclass, int left, int right0, int periodic,
+                                       int y0, int n1) {
   constexpr int K = G::K, TX = G::TX;
   const int l = threadIdx.x % TX, cy = threadIdx.x / TX;
   int cls[K];
@@ -167,85 +169,61 @@ __device__ __forceinline__ void ypass3(const T* __restrict__ sTM, const T* __res
     cls[p] = YIN ? 2 * left + p
                  : tile::row_class(clampi(y0 + cy * K + p, 0, n1 - 1), n1, K, left, right0, periodic);
   constexpr int TXP = G::TXP;
-  // one window at a time (the coefficient rows are reloaded per window)
+  // one window at a time (the scheduling barriers keep the next window's
+  // loads from being hoisted over the current one's products)
   {
     T t[3 * K];
 #pragma unroll
     for (int j = 0; j < 3 * K; ++j) t[j] = sTB[(cy * K + j) * TXP + l];
-    for_pgroups<T, 0, K, 0>(tab, nclass, left, [&](const T* tp, auto pc) {
-      constexpr int p = decltype(pc)::value;
-      S1[p] = band3<T, 0, K, YIN>(tp, sTab, nclass, left, periodic, cls[p], t + p + K, p);
-    });
+#pragma unroll
+    for (int p = 0; p < K; ++p) S1[p] = band3<T, 0, K, YIN>(sTab, nclass, left, periodic, cls[p], t + p + K, p);
   }
+  __builtin_amdgcn_sched_barrier(0);
   {
     T t[3 * K];
 #pragma unroll
     for (int j = 0; j < 3 * K; ++j) t[j] = sTL[(cy * K + j) * TXP + l];
-    for_pgroups<T, 1, K, 0>(tab, nclass, left, [&](const T* tp, auto pc) {
-      constexpr int p = decltype(pc)::value;
-      S1[p] += T(2) * band3<T, 1, K, YIN>(tp, sTab, nclass, left, periodic, cls[p], t + p + K, p);
-    });
-    for_pgroups<T, 0, K, 0>(tab, nclass, left, [&](const T* tp, auto pc) {
-      constexpr int p = decltype(pc)::value;
-      S3[p] = band3<T, 0, K, YIN>(tp, sTab, nclass, left, periodic, cls[p], t + p + K, p);
-    });
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      S1[p] += T(2) * band3<T, 1, K, YIN>(sTab, nclass, left, periodic, cls[p], t + p + K, p);
+      S3[p] = band3<T, 0, K, YIN>(sTab, nclass, left, periodic, cls[p], t + p + K, p);
+    }
   }
+  __builtin_amdgcn_sched_barrier(0);
   {
     T t[5 * K];
 #pragma unroll
     for (int j = 0; j < 5 * K; ++j) t[j] = sTM[(cy * K + j) * TXP + l];
-    for_pgroups<T, 0, K, 0>(tab, nclass, left, [&](const T* tp, auto pc) {
-      constexpr int p = decltype(pc)::value;
-      S2[p] = band3<T, 0, K, YIN>(tp, sTab, nclass, left, periodic, cls[p], t + p + 2 * K, p);
-    });
-    for_pgroups<T, 1, K, 0>(tab, nclass, left, [&](const T* tp, auto pc) {
-      constexpr int p = decltype(pc)::value;
-      S3[p] = T(2) * (S3[p] + band3<T, 1, K, YIN>(tp, sTab, nclass, left, periodic, cls[p], t + p + 2 * K, p));
-    });
-    for_pgroups<T, 2, K, 0>(tab, nclass, left, [&](const T* tp, auto pc) {
-      constexpr int p = decltype(pc)::value;
-      S1[p] += band3<T, 2, K, YIN>(tp, sTab, nclass, left, periodic, cls[p], t + p + 2 * K, p);
-    });
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      const T* v = t + p + 2 * K;
+      S2[p] = band3<T, 0, K, YIN>(sTab, nclass, left, periodic, cls[p], v, p);
+      S3[p] = T(2) * (S3[p] + band3<T, 1, K, YIN>(sTab, nclass, left, periodic, cls[p], v, p));
+      S1[p] += band3<T, 2, K, YIN>(sTab, nclass, left, periodic, cls[p], v, p);
+    }
   }
 }
 
-// Plane zs at cell position PS adds row zs of M_z, L_z, B_z (c* centred on
-// the diagonal) times S1, S3, S2 into the window: slot j is output plane
-// (c - 2) k + j when zs = c k + PS.
+// Plane zs at cell position PS adds row zs of M_z, L_z, B_z (reference
+// scaled, read with wave-uniform addresses) times S1, S3, S2 into the
+// window: slot j is output plane (c - 2) k + j when zs = c k + PS.
+template <typename T, int K, int PS, int OP>
+__device__ __forceinline__ void zterm(T (&acc)[4 * K + 1][K], const T (&S)[K], const T* __restrict__ c) {
+  constexpr int J = 2 * K + PS;
+#pragma unroll
+  for (int o = Band<OP, K>::lo(PS); o <= Band<OP, K>::hi(PS); ++o) {
+    const T cv = c[o];
+#pragma unroll
+    for (int p = 0; p < K; ++p) acc[J + o][p] += cv * S[p];
+  }
+}
 template <typename T, int K, int PS>
 __device__ __forceinline__ void zscatter(T (&acc)[4 * K + 1][K], const T (&S1)[K], const T (&S2)[K],
-                                         const T (&S3)[K], const T* __restrict__ tab, int row, int nclass) {
-  constexpr int J = 2 * K + PS, W = 4 * K + 1, H = 2 * K;
-  {
-    __builtin_amdgcn_sched_barrier(0);
-    const T* cM = tab + opaque(row * W + H);
-#pragma unroll
-    for (int o = Band<0, K>::lo(PS); o <= Band<0, K>::hi(PS); ++o) {
-      const T c = cM[o];
-#pragma unroll
-      for (int p = 0; p < K; ++p) acc[J + o][p] += c * S1[p];
-    }
-  }
-  {
-    __builtin_amdgcn_sched_barrier(0);
-    const T* cL = tab + opaque((nclass + row) * W + H);
-#pragma unroll
-    for (int o = Band<1, K>::lo(PS); o <= Band<1, K>::hi(PS); ++o) {
-      const T c = cL[o];
-#pragma unroll
-      for (int p = 0; p < K; ++p) acc[J + o][p] += c * S3[p];
-    }
-  }
-  {
-    __builtin_amdgcn_sched_barrier(0);
-    const T* cB = tab + opaque((2 * nclass + row) * W + H);
-#pragma unroll
-    for (int o = Band<2, K>::lo(PS); o <= Band<2, K>::hi(PS); ++o) {
-      const T c = cB[o];
-#pragma unroll
-      for (int p = 0; p < K; ++p) acc[J + o][p] += c * S2[p];
-    }
-  }
+                                         const T (&S3)[K], const T* __restrict__ ref, int row, int nclass) {
+  constexpr int W = 4 * K + 1, H = 2 * K;
+  zterm<T, K, PS, 0>(acc, S1, ref + opaque(row * W + H));
+  zterm<T, K, PS, 1>(acc, S3, ref + opaque((nclass + row) * W + H));
+  zterm<T, K, PS, 2>(acc, S2, ref + opaque((2 * nclass + row) * W + H));
 }
 
 // Raw buffer access: an offset at or beyond the buffer's size reads 0 and
@@ -273,8 +251,8 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
 
 template <typename Tin, typename T, class G, bool RES, bool XIN, bool YIN>
 __device__ __forceinline__ void apply3d_tile(const Tin* __restrict__ x, const T* __restrict__ b, T* __restrict__ y,
-                                             int n1, const T* __restrict__ tab, int nclass, int left, int right0,
-                                             int periodic, int x0, int y0, int c0, int c1, T* __restrict__ sX,
+                                             int n1, const T* __restrict__ ref, T hinv, int nclass, int left,
+                                             int right0, int periodic, int x0, int y0, int c0, int c1, T* __restrict__ sX,
                                              T* __restrict__ sTM, T* __restrict__ sTL, T* __restrict__ sTB,
                                              const T* __restrict__ sTab) {
   constexpr int K = G::K, H = G::H, W = G::W, NL = G::NL, NTH = G::NTH;
@@ -347,14 +325,14 @@ __device__ __forceinline__ void apply3d_tile(const Tin* __restrict__ x, const T*
       const int zs = c * K + ps;
       if (zs >= zA && zs <= zB) {
         __syncthreads();  // sX holds plane zs; the previous y passes are done
-        xpass3<T, G, XIN>(sX, sTM, sTL, sTB, tab, sTab, nclass, left, right0, periodic, x0, n1);
+        xpass3<T, G, XIN>(sX, sTM, sTL, sTB, sTab, nclass, left, right0, periodic, x0, n1);
         __syncthreads();
         store_plane();  // plane zs + 1 (unused after zB)
         load_plane(zs + 2);
         T S1[K], S2[K], S3[K];
-        ypass3<T, G, YIN>(sTM, sTL, sTB, S1, S2, S3, tab, sTab, nclass, left, right0, periodic, y0, n1);
+        ypass3<T, G, YIN>(sTM, sTL, sTB, S1, S2, S3, sTab, nclass, left, right0, periodic, y0, n1);
         const int clz = tile::row_class(zs, n1, K, left, right0, periodic);
-        zscatter<T, K, ps>(acc, S1, S2, S3, tab, clz, nclass);
+        zscatter<T, K, ps>(acc, S1, S2, S3, ref, clz, nclass);
       }
       if (ps == 0 && emit_c) {
         // boundary outputs: zero rows give acc = 0, and b reads 0 there
@@ -362,7 +340,10 @@ __device__ __forceinline__ void apply3d_tile(const Tin* __restrict__ x, const T*
         for (int j = 0; j < K; ++j) {
           const __amdgpu_buffer_rsrc_t r = buf(y + (size_t)(ce * K + j) * plane, pout);
 #pragma unroll
-          for (int p = 0; p < K; ++p) buf_store<T>(r, yoff[p], RES ? bq[j][p] - acc[j][p] : acc[j][p]);
+          for (int p = 0; p < K; ++p) {
+            const T a = hinv * acc[j][p];
+            buf_store<T>(r, yoff[p], RES ? bq[j][p] - a : a);
+          }
         }
       }
     });
@@ -407,40 +388,50 @@ inline int face_blocks(int n1) {
   return (int)((3 * (int64_t)n1 * n1 + 16 * NTH - 1) / (16 * NTH));
 }
 
-template <typename Tin, typename T, class G, bool RES>
+// RING = false: one workgroup per (interior tile, z chunk), every x and y
+// row periodic, so all band shapes and coefficients are compile-time.
+// RING = true: the tiles of the boundary ring (per-lane row classes), then
+// the workgroups that zero the faces.  Two launches keep the interior
+// kernel's register budget, and so its occupancy, free of the boundary
+// code.
+template <typename Tin, typename T, class G, bool RES, bool RING>
 __global__ __launch_bounds__(G::NTH) void apply3d_kernel(const Tin* __restrict__ x, const T* __restrict__ b,
-                                                         T* __restrict__ y, int N, int n1, const T* __restrict__ tab,
-                                                         int nclass, int left, int right0, int periodic, int zcc,
-                                                         tile::TileOrder ord) {
-  const int nt = tile::order_blocks(ord);
-  if ((int)blockIdx.x >= nt) {
-    if (blockIdx.y == 0) zero_faces<T, G::NTH>(y, n1, blockIdx.x - nt);
-    return;
-  }
+                                                         T* __restrict__ y, int N, int n1, const T* __restrict__ ref,
+                                                         T hinv, int nclass, int left, int right0, int periodic,
+                                                         int zcc, tile::TileOrder ord) {
   int bx, by;
-  if (!tile::tile_of_block(ord, blockIdx.x, bx, by)) return;
+  if constexpr (RING) {
+    if ((int)blockIdx.x >= ord.nb) {
+      if (blockIdx.y == 0) zero_faces<T, G::NTH>(y, n1, blockIdx.x - ord.nb);
+      return;
+    }
+    tile::tile_of_block(ord, blockIdx.x, bx, by);
+  } else {
+    if (!tile::tile_of_block(ord, ord.nbp + blockIdx.x, bx, by)) return;
+  }
   __shared__ T sX[G::NL * G::NTH + (G::NL * G::NTH / G::RX + 1) * (G::RXP - G::RX)];
   __shared__ T sTM[G::RY * G::TXP];
   __shared__ T sTL[(G::RY - 2 * G::K) * G::TXP];
   __shared__ T sTB[(G::RY - 2 * G::K) * G::TXP];
-  __shared__ T sTab[G::TABMAX];
+  __shared__ T sTab[RING ? G::TABMAX : 1];
   const int x0 = bx * G::TX, y0 = by * G::TY;
   const int c0 = blockIdx.y * zcc, c1 = min(c0 + zcc, N);
-  const bool xin = tile3_xin<G>(periodic, left, right0, x0), yin = tile3_yin<G>(periodic, left, right0, y0);
-  if (!(xin && yin))
-    for (int e = threadIdx.x; e < 3 * nclass * G::W; e += G::NTH) sTab[e] = tab[e];
-  // (the first barrier of the plane loop orders the table copy)
 #define C0IP_TILE(XI, YI)                                                                                        \
-  apply3d_tile<Tin, T, G, RES, XI, YI>(x, b, y, n1, tab, nclass, left, right0, periodic, x0, y0, c0, c1, sX, sTM, \
-                                       sTL, sTB, sTab)
-  if (xin && yin)
+  apply3d_tile<Tin, T, G, RES, XI, YI>(x, b, y, n1, ref, hinv, nclass, left, right0, periodic, x0, y0, c0, c1, sX, \
+                                       sTM, sTL, sTB, sTab)
+  if constexpr (RING) {
+    for (int e = threadIdx.x; e < 3 * nclass * G::W; e += G::NTH) sTab[e] = ref[e];
+    // (the first barrier of the plane loop orders the table copy)
+    const bool xin = tile3_xin<G>(periodic, left, right0, x0), yin = tile3_yin<G>(periodic, left, right0, y0);
+    if (xin)
+      C0IP_TILE(true, false);
+    else if (yin)
+      C0IP_TILE(false, true);
+    else
+      C0IP_TILE(false, false);
+  } else {
     C0IP_TILE(true, true);
-  else if (xin)
-    C0IP_TILE(true, false);
-  else if (yin)
-    C0IP_TILE(false, true);
-  else
-    C0IP_TILE(false, false);
+  }
 #undef C0IP_TILE
 }
 
@@ -462,13 +453,24 @@ hipError_t apply3d_g(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* 
   // planes recomputed per chunk
   int zcc = N;
   while (zcc > 8 && (int64_t)tx * ty * ((N + zcc - 1) / zcc) < 1024) zcc = (zcc + 1) / 2;
-  const dim3 grid(tile::order_blocks(ord) + face_blocks<G::NTH>(n1), (N + zcc - 1) / zcc);
-  if (b)
-    apply3d_kernel<Tin, T, G, true><<<grid, G::NTH, 0, s>>>(x, b, y, N, n1, c.tab, c.nclass, c.left, c.right0,
-                                                            c.periodic, zcc, ord);
-  else
-    apply3d_kernel<Tin, T, G, false><<<grid, G::NTH, 0, s>>>(x, b, y, N, n1, c.tab, c.nclass, c.left, c.right0,
-                                                             c.periodic, zcc, ord);
+  // the ring's slower workgroups take shorter z chunks
+#ifndef C0IP_RING_ZDIV
+#define C0IP_RING_ZDIV 4
+#endif
+  const int zcr = std::max(2, zcc / C0IP_RING_ZDIV);
+  const int nin = tile::order_blocks(ord) - ord.nbp;
+  const dim3 gring(ord.nb + face_blocks<G::NTH>(n1), (N + zcr - 1) / zcr), gin(nin, (N + zcc - 1) / zcc);
+#define C0IP_LAUNCH(RES, RING, GRID, ZC)                                                                         \
+  apply3d_kernel<Tin, T, G, RES, RING><<<GRID, G::NTH, 0, s>>>(x, b, y, N, n1, c.ref, c.hinv, c.nclass, c.left, \
+                                                               c.right0, c.periodic, ZC, ord)
+  if (b) {
+    C0IP_LAUNCH(true, true, gring, zcr);
+    if (nin > 0) C0IP_LAUNCH(true, false, gin, zcc);
+  } else {
+    C0IP_LAUNCH(false, true, gring, zcr);
+    if (nin > 0) C0IP_LAUNCH(false, false, gin, zcc);
+  }
+#undef C0IP_LAUNCH
   return hipGetLastError();
 }
 
@@ -476,6 +478,9 @@ hipError_t apply3d_g(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* 
 
 template <typename Tin, typename T>
 hipError_t launch_apply3d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s) {
+  if (!c.ref) return launch_apply3d_wide<Tin, T>(k, N, c, x, b, y, s);  // not the default penalty
+  // raw buffer offsets of a plane must stay below 2^31 bytes
+  if ((double)(k * N + 1) * (k * N + 1) * sizeof(T) >= 2147483648.0) return hipErrorInvalidValue;
   switch (k) {
     case 2: return apply3d_g<Tin, T, Apply3Cfg<2>::G>(N, c, x, b, y, s);
     case 3: return apply3d_g<Tin, T, Apply3Cfg<3>::G>(N, c, x, b, y, s);
