@@ -125,6 +125,10 @@ hipError_t launch_apply3d_wide(int k, int N, const LevelCoef<T>& c, const Tin* x
 template <typename T>
 hipError_t launch_patch3d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
                           hipStream_t s);
+// owner-computes patch smoother over cubic tiles with per-lane bases (any k; used for k >= 5)
+template <typename T>
+hipError_t launch_patch3d_wide(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
+                               hipStream_t s);
 
 // Lowest levels 0..LT of the 2D V-cycle in one launch, one workgroup per
 // system, every vector in LDS (vtail.hip).  Tables as on the tiled path.

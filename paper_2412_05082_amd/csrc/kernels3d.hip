@@ -333,7 +333,7 @@ hipError_t launch_apply3d_wide(int k, int N, const LevelCoef<T>& c, const Tin* x
 }
 
 template <typename T>
-hipError_t launch_patch3d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
+hipError_t launch_patch3d_wide(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
                           hipStream_t s) {
 #define CALL(K) patch3d_k<T, K>(N, e, r, xin, xout, omega, s)
   C0IP_DISPATCH_K(k, CALL)
@@ -346,9 +346,9 @@ template hipError_t launch_apply3d_wide<float, double>(int, int, const LevelCoef
                                                   const double*, double*, hipStream_t);
 template hipError_t launch_apply3d_wide<float, float>(int, int, const LevelCoef<float>&, const float*, const float*,
                                                  float*, hipStream_t);
-template hipError_t launch_patch3d<double>(int, int, const LevelEig<double>&, const double*, const double*,
+template hipError_t launch_patch3d_wide<double>(int, int, const LevelEig<double>&, const double*, const double*,
                                            double*, double, hipStream_t);
-template hipError_t launch_patch3d<float>(int, int, const LevelEig<float>&, const float*, const float*, float*,
+template hipError_t launch_patch3d_wide<float>(int, int, const LevelEig<float>&, const float*, const float*, float*,
                                           float, hipStream_t);
 
 }  // namespace c0ip
