@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--only", default=None,
                     choices=["matvec_f64", "smoother_f64", "matvec_f32", "smoother_f32", "copy_f64"],
                     help="run only this kernel's timing loop (for counter collection) and print its ms")
+    ap.add_argument("--dim", type=int, default=2, choices=[2, 3],
+                    help="with --only: 3 times the kernel on the 3D Q3 128^3 workload instead")
     ap.add_argument("--variant", type=int, default=None,
                     help="with --only smoother_*: fused smoother tile variant on the finest level")
     return ap.parse_args()
@@ -86,7 +88,9 @@ def only_kernel(args):
 
     import paper_2412_05082_amd as P
     from paper_2412_05082_amd.inputs import seeded_vector
-    dim, k, N = 2, args.k, args.N
+    dim, k, N, omega = 2, args.k, args.N, args.omega
+    if args.dim == 3:  # the 3D Q3 128^3 workload
+        dim, k, N, omega = 3, 3, 128, 0.1
     dev = torch.device("cuda:0")
     x = torch.from_numpy(seeded_vector(dim, k, N, 1)).to(dev)
     b = torch.from_numpy(seeded_vector(dim, k, N, 0)).to(dev)
@@ -94,8 +98,9 @@ def only_kernel(args):
     if args.only.endswith("f32"):
         x, b = x.float(), b.float()
     y = torch.zeros_like(x)
-    pb = P.Problem(dim, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F32)
-    pb.autotune()
+    pb = P.Problem(dim, N, k, omega=omega, vcycle_dtype=P.C0IP_F32)
+    if dim == 2:
+        pb.autotune()
     if args.variant is not None:
         pb.set_variant(args.variant, dtype=P.C0IP_F32 if args.only.endswith("f32") else P.C0IP_F64)
     fn = {"matvec_f64": lambda: pb.apply_A(x, y), "matvec_f32": lambda: pb.apply_A(x, y),
@@ -147,7 +152,8 @@ def cpu_baseline(k, N, omega):
 
 def bench_3d(args, torch, P):
     """3D Q3, 128^3 cells (57,066,625 DoFs): float64 operator, float32 and
-    float64 smoother step, cold buffers (two sets of 456 MB vectors)."""
+    float64 smoother step, cold buffers (two sets of 456 MB vectors), and the
+    MG-FGMRES solve to 1e-8 with a float32 and a float64 V-cycle."""
     from paper_2412_05082_amd.inputs import seeded_vector
     dim, k, N = 3, 3, 128
     dev = torch.device("cuda:0")
@@ -165,10 +171,28 @@ def bench_3d(args, torch, P):
     sets32 = [(x32, torch.zeros(n, dtype=torch.float32, device=dev), b32) for _ in range(2)]
     ms_mv32 = time_kernel(lambda s: pb.apply_A(s[0], s[1]), sets32, reps, torch)
     ms_sm32 = time_kernel(lambda s: pb.smoother_step(s[2], s[0], s[1]), sets32, reps, torch)
-    del sets, sets32, x, b, x32, b32
+    del sets, sets32, x32, b32
     pb.close()
     torch.cuda.empty_cache()
-    out = {"workload": "3D Q3 C0IP biharmonic, 128^3 cells, 57,066,625 DoFs", "dofs": n}
+    # MG-FGMRES(50) solves to 1e-8: float32 V-cycle vs all-float64 (omega = 0.1)
+    solves = {}
+    for name, dt in (("f32_vcycle", P.C0IP_F32), ("f64_vcycle", P.C0IP_F64)):
+        ps = P.Problem(dim, N, k, omega=0.1, vcycle_dtype=dt)
+        xs = torch.zeros(n, dtype=torch.float64, device=dev)
+        ps.solve(b, xs)  # warm-up
+        xs.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ps.solve(b, xs)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        solves[name] = {"s": sec, "iterations": info["iterations"], "dofs_per_s": n / sec}
+        ps.close()
+        del xs
+        torch.cuda.empty_cache()
+    del x, b
+    torch.cuda.empty_cache()
+    out = {"workload": "3D Q3 C0IP biharmonic, 128^3 cells, 57,066,625 DoFs", "dofs": n, "solve": solves}
     for name, ms, byt in [("matvec_f64", ms_mv, 16), ("smoother_f64", ms_sm, 24), ("matvec_f32", ms_mv32, 8),
                           ("smoother_f32", ms_sm32, 12)]:
         out[name] = {"ms": ms, "dofs_per_s": n / (ms * 1e-3), "alg_GBs": byt * n / (ms * 1e-3) / 1e9}

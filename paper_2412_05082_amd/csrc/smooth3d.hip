@@ -326,7 +326,7 @@ __global__ __launch_bounds__(G::NTH) void smooth3d_kernel(const T* __restrict__ 
 
 template <typename T, int K> struct SmoothCfg;
 template <typename T> struct SmoothCfg<T, 2> { using G = SGeo<2, 8>; };
-template <typename T> struct SmoothCfg<T, 3> { using G = SGeo<3, sizeof(T) == 4 ? 6 : 4>; };
+template <typename T> struct SmoothCfg<T, 3> { using G = SGeo<3, 6>; };
 template <typename T> struct SmoothCfg<T, 4> { using G = SGeo<4, sizeof(T) == 4 ? 4 : 2>; };
 
 template <typename T, class G>
