@@ -42,6 +42,28 @@ def test_host_1d_factors_match_exact(k, N):
         assert np.abs(X - Y).max() <= 1e-13 * np.abs(Y).max()
 
 
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_periodic_rows_scale_with_h(k):
+    """With the default penalty gamma = k(k+1) applied as gamma / h, the rows
+    of the periodic classes satisfy M = h M^, L = L^ / h, B = B^ / h^3 with
+    M^, L^, B^ independent of the mesh: the 3D operator uses M^, L^, B^ as
+    compile-time constants and scales its output by 1/h."""
+    ref = None
+    for N in (8, 16, 64):
+        M, L, B = P.host_matrices_1d(k, N)
+        h = 1.0 / N
+        rows = []
+        for p in range(k):
+            g = (N // 2) * k + p  # a node in the middle of the mesh, position p in its cell
+            sl = slice(g - 2 * k, g + 2 * k + 1)
+            rows.append(np.concatenate([M[g, sl] / h, L[g, sl] * h, B[g, sl] * h ** 3]))
+        rows = np.array(rows)
+        if ref is None:
+            ref = rows
+        else:
+            assert np.abs(rows - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("dim,k,N", [(2, 2, 2), (2, 2, 8), (2, 3, 8), (2, 5, 4), (2, 7, 4), (3, 2, 4), (3, 3, 2)])
 def test_host_fdm_inverse_matches_dense_lu(dim, k, N):
     """eq. inverse is an identity: the library's Q D^-1 Q^T equals the
