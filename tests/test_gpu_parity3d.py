@@ -82,7 +82,37 @@ def test_apply_A_3d_n32_sampled(k):
     sn = nodes[: {2: 4, 3: 2, 4: 1}[k]]
     sa = O.avs_nodes_windowed(dim, k, N, x, b, 0.1, sn)
     assert np.abs(sh[sn] - sa).max() <= fp64_tol(dim, k, 8) * np.abs(sa).max()
+    # the float32 smoother step on the same nodes
+    b32 = b.astype(np.float32)
+    xs32 = dev(x32)
+    pb.apply_smoother(dev(b32), xs32)
+    torch.cuda.synchronize()
+    sa32 = O.avs_nodes_windowed(dim, k, N, x32.astype(np.float64), b32.astype(np.float64), 0.1, sn)
+    assert np.abs(host(xs32)[sn] - sa32).max() <= fp32_tol(dim, k, 8) * np.abs(sa32).max()
     assert np.isfinite(yh).all() and np.isfinite(y32h).all() and np.isfinite(sh).all()
+
+
+@pytest.mark.parametrize("k,N", [(2, 8), (3, 4), (4, 4)])
+def test_apply_A_and_smoother_3d_other_penalty(k, N):
+    """A penalty other than k(k+1): the operator takes the table-driven path
+    (no compile-time reference rows); operator and smoother against the
+    oracle assembled with the same penalty."""
+    dim, gamma, om = 3, 2.5 * k * (k + 1), 0.1
+    say("3d other penalty", dim, k, N, gamma)
+    A = O.assemble(dim, k, N, gamma)
+    At = O.assemble(dim, k, N, gamma, bulk="diag")
+    pidx = O.patch_indices(dim, k, N)
+    blocks = O.patch_blocks(At, pidx)
+    x, b = vectors(dim, k, N)
+    pb = P.Problem(dim, N, k, gamma=gamma, omega=om)
+    y = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    pb.apply_A(dev(x), y)
+    xd = dev(x)
+    pb.apply_smoother(dev(b), xd)
+    torch.cuda.synchronize()
+    assert rel_l2(host(y), A @ x) <= 1e-12
+    ref = O.avs_apply(A, blocks, pidx, x, b, om, 1)
+    assert rel_l2(host(xd), ref) <= 10 * fp64_tol(dim, k, N)
 
 
 @pytest.mark.parametrize("dim,k,N", SMALL3)
