@@ -173,6 +173,31 @@ def test_solve_3d(k, N):
         assert np.linalg.norm(b - A @ host(xd)) / np.linalg.norm(b) <= 1.05e-8
 
 
+@pytest.mark.parametrize("dtype", [P.C0IP_F32, P.C0IP_F64])
+def test_solve_3d_q3_n32_sampled_residual(dtype):
+    """3D Q3, 32^3 cells (912,673 DoFs: interior and ring tiles of the
+    operator, interior tiles of the smoother): MG-FGMRES to 1e-8; the
+    residual of the returned solution at sampled rows, from the oracle's
+    windowed rows, obeys |r_i| <= ||r||_2 <= 1e-8 ||b||_2."""
+    dim, k, N = 3, 3, 32
+    say("3d solve sampled residual", dim, k, N, dtype)
+    _, b = vectors(dim, k, N)
+    pb = P.Problem(dim, N, k, omega=0.1, vcycle_dtype=dtype)
+    xd = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    info = pb.solve(dev(b), xd, rtol=1e-8)
+    torch.cuda.synchronize()
+    assert info["converged"] == 1
+    xh = host(xd)
+    n1 = k * N + 1
+    rng = np.random.default_rng(3)
+    rows = _tile_seam_nodes(k, N, rng, 16)
+    i, j, l = rows % n1, (rows // n1) % n1, rows // (n1 * n1)
+    rows = rows[(i > 0) & (i < n1 - 1) & (j > 0) & (j < n1 - 1) & (l > 0) & (l < n1 - 1)]
+    r = b[rows] - O.apply_rows_windowed(dim, k, N, xh, rows)
+    assert np.abs(r).max() <= 1.05e-8 * np.linalg.norm(b)
+    assert np.isfinite(xh).all()
+
+
 def test_full_size_3d_q3_128_sampled():
     """3D Q3, 128^3 cells (57,066,625 DoFs): A x and S(x,b) at sampled DoFs
     (corners, edges, faces, interior) against the windowed oracle."""
