@@ -125,7 +125,7 @@ template <typename T, class G, bool XIN>
 __device__ __forceinline__ void xpass3(const T* __restrict__ sX, T* __restrict__ sTM, T* __restrict__ sTL,
                                        T* __restrict__ sTB, const T* __restrict__ sTab, int nclass, int left,
                                        int right0, int periodic, int x0, int n1) {
-  constexpr int K = G::K, CW = G::CW, H = G::H, TX = G::TX;
+  constexpr int K = G::K, CW = G::CW, H = G::H;
   constexpr int LO = Band<2, K>::win_lo(0), HI = Band<2, K>::win_hi() + (CW - 1) * K;
   for (int it = threadIdx.x; it < G::NXI; it += G::NTH) {
     const int g = it / G::RY, r = it - g * G::RY;
@@ -255,7 +255,7 @@ __device__ __forceinline__ void apply3d_tile(const Tin* __restrict__ x, const T*
                                              int right0, int periodic, int x0, int y0, int c0, int c1, T* __restrict__ sX,
                                              T* __restrict__ sTM, T* __restrict__ sTL, T* __restrict__ sTB,
                                              const T* __restrict__ sTab) {
-  constexpr int K = G::K, H = G::H, W = G::W, NL = G::NL, NTH = G::NTH;
+  constexpr int K = G::K, H = G::H, NL = G::NL, NTH = G::NTH;
   const int NK = n1 - 1;
   const size_t plane = (size_t)n1 * n1;
   const unsigned pin = (unsigned)(plane * sizeof(Tin)), pout = (unsigned)(plane * sizeof(T));

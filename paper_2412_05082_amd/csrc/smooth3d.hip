@@ -112,8 +112,8 @@ __device__ __forceinline__ void pass_xy(T* __restrict__ slot, const T* __restric
 
 template <typename T, class G, bool UNI>
 __device__ __forceinline__ void smooth3d_tile(const T* __restrict__ r, const T* __restrict__ xin, T* __restrict__ xout,
-                                              int N, const T* __restrict__ Qg, const T* __restrict__ lamg, T omega,
-                                              int cx0, int cy0, int c0, int c1, T* __restrict__ sF,
+                                              int N, const T* __restrict__ Qg, T omega, int cx0, int cy0, int c0,
+                                              int c1, T* __restrict__ sF,
                                               T* __restrict__ sR, const T* __restrict__ sQ,
                                               const T* __restrict__ sLam) {
   constexpr int K = G::K, n = G::n, NN = G::NN, NTH = G::NTH, NO = G::NO, RING = 2 * K - 1;
@@ -293,8 +293,7 @@ __device__ __forceinline__ void zero_faces3(T* __restrict__ y, int n1, int fb) {
 template <typename T, class G>
 __global__ __launch_bounds__(G::NTH) void smooth3d_kernel(const T* __restrict__ r, const T* __restrict__ xin,
                                                           T* __restrict__ xout, int N, const T* __restrict__ Qg,
-                                                          const T* __restrict__ lamg, T omega, int tx, int zcc,
-                                                          int nface) {
+                                                          const T* __restrict__ lamg, T omega, int tx, int zcc) {
   const int n1 = G::K * N + 1;
   const int nt = tx * tx;
   if ((int)blockIdx.x >= nt) {
@@ -317,11 +316,11 @@ __global__ __launch_bounds__(G::NTH) void smooth3d_kernel(const T* __restrict__ 
   const bool uni = kUniFits && cx0 >= 2 && cx0 + G::TC <= N - 2 && cy0 >= 2 && cy0 + G::TC <= N - 2;
   if constexpr (kUniFits) {
     if (uni) {
-      smooth3d_tile<T, G, true>(r, xin, xout, N, Qg, lamg, omega, cx0, cy0, c0, c1, sF, sR, sQ, sLam);
+      smooth3d_tile<T, G, true>(r, xin, xout, N, Qg, omega, cx0, cy0, c0, c1, sF, sR, sQ, sLam);
       return;
     }
   }
-  smooth3d_tile<T, G, false>(r, xin, xout, N, Qg, lamg, omega, cx0, cy0, c0, c1, sF, sR, sQ, sLam);
+  smooth3d_tile<T, G, false>(r, xin, xout, N, Qg, omega, cx0, cy0, c0, c1, sF, sR, sQ, sLam);
 }
 
 template <typename T, int K> struct SmoothCfg;
@@ -337,7 +336,7 @@ hipError_t smooth3d_g(int N, const LevelEig<T>& e, const T* r, const T* xin, T* 
   while (zcc > 4 && (int64_t)tx * tx * ((N + zcc - 1) / zcc) < 2048) zcc = (zcc + 1) / 2;
   const int nface = (int)((3 * (int64_t)n1 * n1 + 16 * G::NTH - 1) / (16 * G::NTH));
   const dim3 grid(tx * tx + nface, (N + zcc - 1) / zcc);
-  smooth3d_kernel<T, G><<<grid, G::NTH, 0, s>>>(r, xin, xout, N, e.Q, e.lam, omega, tx, zcc, nface);
+  smooth3d_kernel<T, G><<<grid, G::NTH, 0, s>>>(r, xin, xout, N, e.Q, e.lam, omega, tx, zcc);
   return hipGetLastError();
 }
 
