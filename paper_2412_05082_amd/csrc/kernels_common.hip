@@ -12,6 +12,21 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Division by a divisor fixed for a launch (Granlund-Montgomery): q = n / d
+// for 0 <= n < 2^31 and 1 <= d < 2^31 with one high multiply, an add and a
+// shift instead of a 64-bit division per element.
+struct FastDiv {
+  uint32_t d = 1, m = 0, l = 0;
+  FastDiv() = default;
+  explicit FastDiv(uint32_t dv) : d(dv) {
+    while ((1ull << l) < d) ++l;
+    m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    return (uint32_t)(((uint64_t)__umulhi(n, m) + n) >> l);
+  }
+};
+
 inline int grid_for(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   if (b > (1 << 20)) b = 1 << 20;
@@ -20,61 +35,98 @@ inline int grid_for(int64_t n) {
 }
 
 // out[i_f] (+)= sum_a T[s][p][a] in[cc k + a],  fine node i_f = (2cc+s) k + p.
+// One item per (inner index, coarse cell, outer index), item indices below
+// 2^31 (checked by the launcher): ii = idx mod inner, cc = (idx / inner) mod
+// ncell, io = idx / (inner ncell), by fixed divisors.  The item's positions
+// in the cell are compile-time, so the table entries are wave-uniform.
+
+// Prolongation along one axis: coarse cell cc (coarse nodes cc k .. cc k + k)
+// gives the 2k fine nodes of fine cells 2cc, 2cc+1:
+//   out[(2cc+s) k + p] (+)= sum_a T[s][p][a] in[cc k + a];
+// the cell cc = Nc - 1 also writes the last fine node, and the first and
+// last fine nodes (boundary) get 0.
 template <typename T, int K, bool ACC>
 __global__ __launch_bounds__(kThreads) void prolong1d_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                              int64_t inner, int nin, int nout, int64_t outer,
-                                                             const T* __restrict__ tab) {
-  const int64_t total = inner * nout * outer;
-  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * kThreads) {
-    const int64_t ii = idx % inner, rest = idx / inner;
-    const int f = (int)(rest % nout);
-    const int64_t io = rest / nout;
-    T v = 0;
-    if (f > 0 && f < nout - 1) {
-      const int cf = f / K, p = f - cf * K, cc = cf >> 1, s = cf & 1;
-      const T* base = in + ii + inner * ((int64_t)cc * K + (int64_t)nin * io);
-      const T* tb = tab + (s * K + p) * (K + 1);
+                                                             const T* __restrict__ tab, FastDiv dinner,
+                                                             FastDiv dcell) {
+  const int ncell = nin / K;  // Nc
+  const uint32_t total = (uint32_t)(inner * ncell * outer);
+  for (uint32_t idx = blockIdx.x * kThreads + threadIdx.x; idx < total; idx += gridDim.x * kThreads) {
+    const uint32_t rest = dinner.div(idx), iq = dcell.div(rest);
+    const int64_t ii = idx - rest * (uint32_t)inner;
+    const int cc = (int)(rest - iq * (uint32_t)ncell);
+    const int64_t io = iq;
+    const T* base = in + ii + inner * ((int64_t)cc * K + (int64_t)nin * io);
+    T c[K + 1];
 #pragma unroll
-      for (int a = 0; a <= K; ++a) v += tb[a] * base[a * inner];
-    }
-    T* o = out + ii + inner * ((int64_t)f + (int64_t)nout * io);
-    if (ACC)
-      *o += v;
-    else
-      *o = v;
+    for (int a = 0; a <= K; ++a) c[a] = base[a * inner];
+    T* o = out + ii + inner * ((int64_t)nout * io);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        const int f = (2 * cc + s) * K + p;
+        T v = 0;
+#pragma unroll
+        for (int a = 0; a <= K; ++a) v += tab[(s * K + p) * (K + 1) + a] * c[a];
+        if (f == 0) v = T(0);
+        if (ACC)
+          o[inner * f] += v;
+        else
+          o[inner * f] = v;
+      }
+    if (cc == ncell - 1 && !ACC) o[inner * (nout - 1)] = T(0);
   }
 }
 
-// out[I] = sum over fine nodes of P[i_f][I] in[i_f]; coarse node I = cc k + a.
+// Restriction along one axis (the transpose): coarse cell cc gives the
+// coarse nodes cc k + a, a < k, from the fine nodes of fine cells 2cc-2 ..
+// 2cc+1 (the vertex a = 0 also collects the coarse basis of cell cc-1):
+//   out[cc k + a] = sum_{s,p} T[s][p][a] in[(2cc+s) k + p]
+//                 + [a = 0] sum_{s,p} T[s][p][k] in[(2cc-2+s) k + p];
+// cc = Nc writes the last coarse node; boundary nodes get 0.
 template <typename T, int K>
 __global__ __launch_bounds__(kThreads) void restrict1d_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                               int64_t inner, int nin, int nout, int64_t outer,
-                                                              const T* __restrict__ tab) {
-  const int64_t total = inner * nout * outer;
-  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * kThreads) {
-    const int64_t ii = idx % inner, rest = idx / inner;
-    const int I = (int)(rest % nout);
-    const int64_t io = rest / nout;
-    T v = 0;
-    if (I > 0 && I < nout - 1) {
-      const int cc = I / K, a = I - cc * K;
-      const T* base = in + ii + inner * ((int64_t)nin * io);
+                                                              const T* __restrict__ tab, FastDiv dinner,
+                                                              FastDiv dcell) {
+  const int ncell = nout / K + 1;  // Nc + 1
+  const uint32_t total = (uint32_t)(inner * ncell * outer);
+  for (uint32_t idx = blockIdx.x * kThreads + threadIdx.x; idx < total; idx += gridDim.x * kThreads) {
+    const uint32_t rest = dinner.div(idx), iq = dcell.div(rest);
+    const int64_t ii = idx - rest * (uint32_t)inner;
+    const int cc = (int)(rest - iq * (uint32_t)ncell);
+    const int64_t io = iq;
+    T* o = out + ii + inner * ((int64_t)nout * io);
+    if (cc == ncell - 1) {  // the last coarse node (boundary)
+      o[inner * (int64_t)(nout - 1)] = T(0);
+      continue;
+    }
+    const T* base = in + ii + inner * ((int64_t)nin * io);
+    // fine nodes (2cc-2) k .. (2cc+2) k - 1 (the lower half only for cc >= 1)
+    T w[4 * K];
+#pragma unroll
+    for (int j = 0; j < 4 * K; ++j) {
+      const int f = (2 * cc - 2) * K + j;
+      w[j] = (f >= 0 && f < nin) ? base[inner * (int64_t)f] : T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      T v = 0;
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int p = 0; p < K; ++p)
-          v += tab[(s * K + p) * (K + 1) + a] * base[inner * ((int64_t)(2 * cc + s) * K + p)];
+        for (int p = 0; p < K; ++p) v += tab[(s * K + p) * (K + 1) + a] * w[2 * K + s * K + p];
       if (a == 0) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-          for (int p = 0; p < K; ++p)
-            v += tab[(s * K + p) * (K + 1) + K] * base[inner * ((int64_t)(2 * cc - 2 + s) * K + p)];
+          for (int p = 0; p < K; ++p) v += tab[(s * K + p) * (K + 1) + K] * w[s * K + p];
       }
+      const int I = cc * K + a;
+      o[inner * (int64_t)I] = (I == 0) ? T(0) : v;
     }
-    out[ii + inner * ((int64_t)I + (int64_t)nout * io)] = v;
   }
 }
 
@@ -90,8 +142,11 @@ hipError_t restrict_k(int dim, int Nc, const T* tab, const T* rf, T* bc, T* scra
     for (int m = 0; m < ax; ++m) inner *= sz[m];
     for (int m = ax + 1; m < dim; ++m) outer *= sz[m];
     T* dst = (ax == dim - 1) ? bc : bufs[ax & 1];
-    const int64_t total = inner * nc * outer;
-    restrict1d_kernel<T, K><<<grid_for(total), kThreads, 0, s>>>(src, dst, inner, (int)nf, (int)nc, outer, tab);
+    const int64_t total = inner * (Nc + 1) * outer;  // items: coarse cells 0..Nc
+    if (inner * nf * outer >= (1ll << 31)) return hipErrorInvalidValue;
+    restrict1d_kernel<T, K><<<grid_for(total), kThreads, 0, s>>>(src, dst, inner, (int)nf, (int)nc, outer, tab,
+                                                                 FastDiv((uint32_t)inner),
+                                                                 FastDiv((uint32_t)(Nc + 1)));
     sz[ax] = nc;
     src = dst;
   }
@@ -108,14 +163,16 @@ hipError_t prolong_k(int dim, int Nc, const T* tab, const T* ec, T* xf, T* scrat
     int64_t inner = 1, outer = 1;
     for (int m = 0; m < ax; ++m) inner *= sz[m];
     for (int m = ax + 1; m < dim; ++m) outer *= sz[m];
-    const int64_t total = inner * nf * outer;
+    const int64_t total = inner * Nc * outer;  // items: coarse cells 0..Nc-1
+    if (inner * nf * outer >= (1ll << 31)) return hipErrorInvalidValue;
+    const FastDiv di((uint32_t)inner), dn((uint32_t)Nc);
     if (ax == dim - 1) {
       prolong1d_kernel<T, K, true><<<grid_for(total), kThreads, 0, s>>>(src, xf, inner, (int)nc, (int)nf, outer,
-                                                                         tab);
+                                                                         tab, di, dn);
     } else {
       T* dst = bufs[ax & 1];
       prolong1d_kernel<T, K, false><<<grid_for(total), kThreads, 0, s>>>(src, dst, inner, (int)nc, (int)nf,
-                                                                          outer, tab);
+                                                                          outer, tab, di, dn);
       src = dst;
     }
     sz[ax] = nf;
