@@ -453,11 +453,9 @@ hipError_t apply3d_g(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* 
   // planes recomputed per chunk
   int zcc = N;
   while (zcc > 8 && (int64_t)tx * ty * ((N + zcc - 1) / zcc) < 1024) zcc = (zcc + 1) / 2;
-  // the ring's slower workgroups take shorter z chunks
-#ifndef C0IP_RING_ZDIV
-#define C0IP_RING_ZDIV 4
-#endif
-  const int zcr = std::max(2, zcc / C0IP_RING_ZDIV);
+  // the ring's slower workgroups take shorter z chunks: 16 per column
+  // (measured best for k = 3 at 32^3, 64^3 and 128^3 cells)
+  const int zcr = std::max(2, N / 16);
   const int nin = tile::order_blocks(ord) - ord.nbp;
   const dim3 gring(ord.nb + face_blocks<G::NTH>(n1), (N + zcr - 1) / zcr), gin(nin, (N + zcc - 1) / zcc);
 #define C0IP_LAUNCH(RES, RING, GRID, ZC)                                                                         \
