@@ -216,7 +216,8 @@ def test_full_size_sampled_parity(k, N):
 
 def test_abi_rejects_bad_arguments():
     say("abi errors")
-    for kw in [dict(dim=4, N=8, k=3), dict(dim=2, N=6, k=3), dict(dim=2, N=8, k=1), dict(dim=2, N=8, k=8)]:
+    for kw in [dict(dim=4, N=8, k=3), dict(dim=2, N=6, k=3), dict(dim=3, N=40, k=2), dict(dim=2, N=8, k=1),
+               dict(dim=2, N=8, k=8)]:
         with pytest.raises(P.C0ipError) as e:
             P.Problem(kw["dim"], kw["N"], kw["k"])
         assert e.value.status == -1

@@ -92,6 +92,31 @@ def test_apply_A_3d_n32_sampled(k):
     assert np.isfinite(yh).all() and np.isfinite(y32h).all() and np.isfinite(sh).all()
 
 
+@pytest.mark.parametrize("k", [3, 2])
+def test_apply_A_3d_ring_chunks_sampled(k):
+    """64^3 cells: ring z chunks of 4 planes (N / 16) and interior chunks of
+    8; float64 and float32 A x at nodes on the tile and chunk seams."""
+    N = 64
+    dim = 3
+    say("3d apply_A ring chunks", dim, k, N)
+    x, _ = vectors(dim, k, N)
+    pb = P.Problem(dim, N, k)
+    y = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    pb.apply_A(dev(x), y)
+    x32 = x.astype(np.float32)
+    y32 = torch.empty(x.size, dtype=torch.float32, device="cuda")
+    pb.apply_A(dev(x32), y32)
+    torch.cuda.synchronize()
+    yh, y32h = host(y), host(y32)
+    nodes = _tile_seam_nodes(k, N, np.random.default_rng(13), 32)
+    ya = O.apply_rows_windowed(dim, k, N, x, nodes)
+    scale = np.abs(ya).max()
+    assert np.abs(yh[nodes] - ya).max() <= 1e-12 * scale
+    ya32 = O.apply_rows_windowed(dim, k, N, x32.astype(np.float64), nodes)
+    assert np.abs(y32h[nodes] - ya32).max() <= 1e-5 * scale
+    assert np.isfinite(yh).all() and np.isfinite(y32h).all()
+
+
 @pytest.mark.parametrize("k,N", [(2, 8), (3, 4), (4, 4)])
 def test_apply_A_and_smoother_3d_other_penalty(k, N):
     """A penalty other than k(k+1): the operator takes the table-driven path
