@@ -46,7 +46,8 @@ __all__ = [
     "boundary_mask", "assemble", "Window", "patch_vertices", "patch_indices",
     "patch_blocks", "avs_apply", "prolongation_1d", "prolongation", "Hierarchy",
     "fgmres", "fractional_iterations", "load_vector", "manufactured_rhs", "energy_error",
-    "exact_solution_nodal", "window_around", "apply_rows_windowed", "avs_nodes_windowed",
+    "exact_solution_nodal", "window_around", "apply_rows_windowed", "avs_nodes_windowed", "apply_blocked",
+    "mvs_colors", "mvs_apply", "mvs_sequential",
 ]
 
 
@@ -353,6 +354,58 @@ def avs_apply(A, blocks, pidx, x, b, omega, steps=1, x_is_zero=False):
     return x
 
 
+def mvs_colors(dim: int, N: int, vertices=None) -> np.ndarray:
+    """Colour of each interior vertex for the coloured multiplicative smoother
+    (Sec. 3, Fig. 2): first the 2^dim classes of vertex parity, whose patches
+    do not overlap, then a red-black split of each class by the parity of
+    sum_m floor(v_m / 2), so that two patches of one colour never touch
+    across a face (their DoF sets are then A-orthogonal).  Colour =
+    sum_m (v_m mod 2) 2^m + 2^dim (sum_m floor(v_m / 2) mod 2): 8 colours in
+    two and 16 in three dimensions; the colours are swept in this order
+    (reading: the paper fixes the colouring, not the order)."""
+    v = patch_vertices(dim, N) if vertices is None else np.atleast_2d(vertices)
+    base = sum((v[:, m] % 2) << m for m in range(dim))
+    rb = (v // 2).sum(axis=1) % 2
+    return base + (rb << dim)
+
+
+def mvs_apply(A, blocks, pidx, colors, x, b, omega, steps=1, x_is_zero=False):
+    """Coloured multiplicative vertex-patch smoother (Sec. 3): per step, for
+    each colour c = 0, 1, ... in turn,
+    x <- x + omega * sum_{v of colour c} R_v^T A_v^{-1} R_v (b - A x)
+    (sign reading G4), the residual taken after the previous colour.  Patch
+    solves by dense LU; the arithmetic type is that of ``blocks``."""
+    dt = blocks.dtype
+    x = np.zeros_like(b, dtype=dt) if x_is_zero else np.array(x, dtype=dt)
+    b = np.asarray(b, dtype=dt)
+    w = dt.type(omega)
+    ncol = int(colors.max()) + 1 if colors.size else 0
+    for s in range(steps):
+        for c in range(ncol):
+            sel = np.where(colors == c)[0]
+            if sel.size == 0:
+                continue
+            r = b - (A @ x).astype(dt)
+            u = np.linalg.solve(blocks[sel], r[pidx[sel]][..., None])[..., 0]
+            corr = np.zeros_like(x)
+            np.add.at(corr, pidx[sel].ravel(), u.ravel())
+            x = x + w * corr
+    return x
+
+
+def mvs_sequential(A, blocks, pidx, order, x, b, omega, steps=1, x_is_zero=False):
+    """The multiplicative vertex-patch smoother as defined before colouring
+    (Sec. 3): one patch at a time in the given vertex order,
+    x <- x + omega R_v^T A_v^{-1} R_v (b - A x).  Plain definition, for small
+    meshes only."""
+    x = np.zeros_like(b, dtype=np.float64) if x_is_zero else np.array(x, dtype=np.float64)
+    for s in range(steps):
+        for v in order:
+            r = b - A @ x
+            x[pidx[v]] += omega * np.linalg.solve(blocks[v], r[pidx[v]])
+    return x
+
+
 # --------------------------------------------------------------------------
 # Transfers (Sec. 3: prolongation = embedding, restriction = transpose)
 # --------------------------------------------------------------------------
@@ -419,6 +472,35 @@ def apply_rows_windowed(dim, k, N, x, rows, gamma=None):
     return out
 
 
+def apply_blocked(dim, k, N, X, block=64, gamma=None, absolute=False):
+    """A X (or |A| X with ``absolute``) for a full-size mesh without holding A:
+    the mesh is cut into boxes of ``block`` cells per direction; each box,
+    widened by two cells (every row of a node owned by the box then lies in
+    the widened window, see Window.exact_rows), is assembled on its own and
+    gives the rows of the nodes it owns.  A node is owned by the box holding
+    cell min(i // k, N - 1) in every direction.  X: (n,) or (n, m)."""
+    X = np.asarray(X, dtype=np.float64)
+    n1 = k * N + 1
+    Y = np.zeros_like(X)
+    own_cell = np.minimum(np.arange(n1) // k, N - 1)
+    starts = list(range(0, N, block))
+    for corner in np.stack(np.meshgrid(*[starts] * dim, indexing="ij"), -1).reshape(-1, dim):
+        lo = [max(int(c) - 2, 0) for c in corner]
+        hi = [min(int(c) + block + 2, N) for c in corner]
+        win = Window(dim, k, N, lo, hi)
+        owned = np.ones(win.size, dtype=bool)
+        for m in range(dim):
+            oc = own_cell[win.gmulti[:, m]]
+            owned &= (oc >= corner[m]) & (oc < min(corner[m] + block, N))
+        if not np.all(win.exact_rows(1)[owned]):
+            raise AssertionError("block window too small")
+        A = assemble(dim, k, N, gamma, window=win)
+        if absolute:
+            A = abs(A)
+        Y[win.gidx[owned]] = (A @ X[win.gidx])[owned]
+    return Y
+
+
 def avs_nodes_windowed(dim, k, N, x, b, omega, nodes, gamma=None, x_is_zero=False):
     """One additive smoothing step S(x, b) (or S(0, b)) evaluated at selected
     nodes of the full-size mesh: residual, patch solves by dense LU and the
@@ -462,18 +544,23 @@ class Hierarchy:
     2^dim cells, one vertex patch; Sec. 5.1).  Each level re-assembles A_l
     from the bilinear form.  ``local`` = 'inexact' uses the separable patch
     matrices, 'exact' the restriction of A_l.  ``dtype`` float32 runs the
-    whole V-cycle in single precision except the coarse solve (Sec. 5.2)."""
+    whole V-cycle in single precision except the coarse solve (Sec. 5.2).
+    ``smoother`` = 'avs' (additive) or 'mvs' (coloured multiplicative, the
+    same colour order before and after the coarse correction)."""
 
     def __init__(self, dim, k, N, gamma=None, omega=0.25, pre=1, post=1,
-                 local="inexact", dtype=np.float64, coarse="cholesky"):
+                 local="inexact", dtype=np.float64, coarse="cholesky", smoother="avs"):
         L = int(round(math.log2(N))) - 1
         if 2 ** (L + 1) != N or L < 0:
             raise ValueError("N must be a power of two >= 2")
         self.dim, self.k, self.N, self.L = dim, k, N, L
         self.omega, self.pre, self.post = omega, pre, post
+        if smoother not in ("avs", "mvs"):
+            raise ValueError(smoother)
+        self.smoother = smoother
         self.dtype = np.dtype(dtype)
         self.coarse_mode = coarse
-        self.A, self.Alow, self.blocks, self.pidx, self.P = [], [], [], [], [None]
+        self.A, self.Alow, self.blocks, self.pidx, self.P, self.colors = [], [], [], [], [None], []
         for l in range(L + 1):
             Nl = 2 ** (l + 1)
             A = assemble(dim, k, Nl, gamma)
@@ -483,6 +570,7 @@ class Hierarchy:
             self.Alow.append(A.astype(self.dtype))
             self.blocks.append(patch_blocks(At, pidx).astype(self.dtype))
             self.pidx.append(pidx)
+            self.colors.append(mvs_colors(dim, Nl))
             if l > 0:
                 self.P.append(prolongation(dim, k, Nl // 2).astype(self.dtype))
         free0 = ~boundary_mask(dim, k, 2)
@@ -499,6 +587,9 @@ class Hierarchy:
         return avs_apply(self.Alow[0], self.blocks[0], self.pidx[0], None, b0, 1.0, 1, x_is_zero=True)
 
     def smooth(self, l, x, b, steps, x_is_zero=False):
+        if self.smoother == "mvs":
+            return mvs_apply(self.Alow[l], self.blocks[l], self.pidx[l], self.colors[l], x, b, self.omega, steps,
+                             x_is_zero)
         return avs_apply(self.Alow[l], self.blocks[l], self.pidx[l], x, b, self.omega, steps, x_is_zero)
 
     def mg(self, l, b):

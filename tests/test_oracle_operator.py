@@ -142,3 +142,15 @@ def test_windowed_sampled_outputs_equal_global(dim, k, N):
     S = O.avs_apply(A, O.patch_blocks(At, pidx), pidx, x, b, 0.25)
     Sw = O.avs_nodes_windowed(dim, k, N, x, b, 0.25, nodes)
     assert np.abs(Sw - S[nodes]).max() <= 1e-13 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("dim,k,N,block", [(2, 3, 16, 5), (2, 2, 8, 3), (3, 2, 6, 4)])
+def test_apply_blocked_equals_global_apply(dim, k, N, block):
+    """The row-blocked apply (windows of cells, each assembled on its own)
+    gives exactly the rows of the globally assembled matrix, for A and |A|,
+    with ragged last blocks and several right-hand sides."""
+    A = O.assemble(dim, k, N)
+    X = np.random.default_rng(4).uniform(-1, 1, (A.shape[0], 2))
+    assert np.abs(O.apply_blocked(dim, k, N, X, block=block) - A @ X).max() <= 1e-12 * np.abs(A @ X).max()
+    Ya = O.apply_blocked(dim, k, N, np.abs(X), block=block, absolute=True)
+    assert np.abs(Ya - abs(A) @ np.abs(X)).max() <= 1e-12 * Ya.max()
