@@ -47,7 +47,7 @@ __all__ = [
     "patch_blocks", "avs_apply", "prolongation_1d", "prolongation", "Hierarchy",
     "fgmres", "fractional_iterations", "load_vector", "manufactured_rhs", "energy_error",
     "exact_solution_nodal", "window_around", "apply_rows_windowed", "avs_nodes_windowed", "apply_blocked",
-    "mvs_colors", "mvs_apply", "mvs_sequential",
+    "mvs_colors", "mvs_apply", "mvs_sequential", "fcg",
 ]
 
 
@@ -676,6 +676,40 @@ def fgmres(A, b, precond=None, rtol=1e-8, restart=50, maxiter=1000, x0=None):
     return x, {"iterations": its, "converged": bool(converged), "history": hist,
                "rel_res_est": hist[-1] / bnorm if bnorm else 0.0,
                "rel_res_true": beta / bnorm if bnorm else 0.0}
+
+
+def fcg(A, b, precond=None, rtol=1e-8, maxiter=1000, x0=None):
+    """Flexible conjugate gradients in float64 with one retained direction
+    (the paper's Krylov method for the symmetric additive smoother, Sec.
+    5.1; the flexible form tolerates a preconditioner that is only nearly
+    symmetric, such as a float32 V-cycle):
+        z = M(r);  p = z - (z.q_old / p_old.q_old) p_old  (p = z at first);
+        q = A p;  alpha = (r.p) / (p.q);  x += alpha p;  r -= alpha q,
+    stopping when the recursive residual |r| <= rtol |b| (x0 = 0 unless
+    given).  Returns (x, info) with the true residual of x."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    bnorm = np.linalg.norm(b)
+    if precond is None:
+        precond = lambda v: v  # noqa: E731
+    r = b - A @ x
+    hist = [np.linalg.norm(r)]
+    p = q = None
+    pq = None
+    its = 0
+    while hist[-1] > rtol * bnorm and its < maxiter:
+        z = precond(r)
+        p = z.copy() if p is None else z - (z @ q) / pq * p
+        q = A @ p
+        pq = p @ q
+        alpha = (r @ p) / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        its += 1
+        hist.append(np.linalg.norm(r))
+    rt = np.linalg.norm(b - A @ x)
+    return x, {"iterations": its, "converged": bool(hist[-1] <= rtol * bnorm), "history": hist,
+               "rel_res_est": hist[-1] / bnorm if bnorm else 0.0, "rel_res_true": rt / bnorm if bnorm else 0.0}
 
 
 def fractional_iterations(n: int, rn: float, r0: float) -> float:

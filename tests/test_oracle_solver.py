@@ -5,6 +5,7 @@ import scipy.linalg as sla
 import scipy.sparse.linalg as spla
 
 import oracle as O
+from paper_2412_05082_amd.inputs import seeded_vector
 from tests import sym1d
 
 
@@ -152,3 +153,33 @@ def test_literal_damping_07_does_not_converge():
     H = O.Hierarchy(dim, k, N, omega=0.7)
     x, info = O.fgmres(A, b, H.vcycle, rtol=1e-8, maxiter=100)
     assert not info["converged"]
+
+
+def test_fcg_identity_terminates_and_matches_direct_solve():
+    """Flexible CG with the identity preconditioner is plain CG: on the
+    9-unknown level-0 system it terminates (to rounding) within 9 steps, and
+    on a small mesh it reaches the sparse direct solution."""
+    for k, N, nmax in [(2, 2, 9), (3, 4, None)]:
+        A = O.assemble(2, k, N)
+        b = np.random.default_rng(3).uniform(-1, 1, A.shape[0])
+        free = ~O.boundary_mask(2, k, N)
+        b[~free] = 0.0
+        x, info = O.fcg(A, b, rtol=1e-13, maxiter=5000)
+        xd = np.zeros_like(b)
+        xd[free] = spla.spsolve(A[free][:, free].tocsc(), b[free])
+        assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+        if nmax is not None:
+            assert info["iterations"] <= nmax
+
+
+def test_fcg_with_vcycle_converges_like_fgmres():
+    """With the symmetric additive V-cycle, flexible CG converges to 1e-8 in a
+    number of iterations close to FGMRES (the paper uses CG for AVS)."""
+    dim, k, N = 2, 3, 16
+    A = O.assemble(dim, k, N)
+    b = seeded_vector(dim, k, N, 0)
+    H = O.Hierarchy(dim, k, N, omega=0.25)
+    _, ig = O.fgmres(A, b, H.vcycle, rtol=1e-8, restart=50)
+    x, ic = O.fcg(A, b, H.vcycle, rtol=1e-8)
+    assert ic["converged"] and ic["rel_res_true"] <= 1.05e-8
+    assert abs(ic["iterations"] - ig["iterations"]) <= 3
