@@ -81,7 +81,18 @@ typedef struct {
  *   run as one launch of a single workgroup per system, all their vectors
  *   in LDS (same operations, fewer launches).  -1 = as many levels as fit
  *   in LDS; 0 = none (every level on the tiled kernels); m > 0 = at most
- *   levels 0..m-1.  Ignored in 3D and for degree > 4. */
+ *   levels 0..m-1.  Ignored in 3D and for degree > 4.
+ * smoother: 0 = additive vertex-patch Schwarz (AVS); 1 = coloured
+ *   multiplicative vertex-patch Schwarz (MVS, Sec. 3 and Fig. 2): the
+ *   vertices are split into 8 colours (2^d vertex-parity classes, each
+ *   split red-black), patches of one colour share no node and no entry of
+ *   A couples them; a step visits the colours in order c = 0..7 and for
+ *   each forms the residual of the current iterate and adds omega times the
+ *   local solves of that colour's patches (the paper uses omega = 1 in 2D).
+ *   Colour of vertex v: sum_m (v_m mod 2) 2^m + 2^d ((sum_m floor(v_m / 2))
+ *   mod 2).  MVS needs scatter_mode 0 (C0IP_EINVAL otherwise) and is built
+ *   for 2D meshes (C0IP_EUNSUPPORTED in 3D and for batched solves).  Other
+ *   values: C0IP_EINVAL. */
 typedef struct {
   double omega;
   int pre_steps, post_steps;
@@ -89,6 +100,7 @@ typedef struct {
   int coarse_mode;
   int scatter_mode;
   int tail_levels;
+  int smoother;
 } c0ip_mg_opts;
 
 /* Flexible GMRES options (Sec. 5.1: relative residual reduction 1e-8).
@@ -115,7 +127,7 @@ typedef struct {
 /* Create a problem: level hierarchy, 1D matrices, patch eigenbases, coarse
  * inverse, device tables and work space (Sec. 3-4).  opts may be NULL
  * (omega 1/4 in 2D and 0.1 in 3D, 1 pre- and 1 post-step, float32
- * V-cycle, exact coarse solve, tail_levels -1).  hip_stream is a hipStream_t or NULL.
+ * V-cycle, exact coarse solve, tail_levels -1, additive smoother).  hip_stream is a hipStream_t or NULL.
  * On success *out owns all device memory it allocated. */
 c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, void* hip_stream,
                         c0ip_problem** out);
@@ -128,15 +140,16 @@ c0ip_status c0ip_num_dofs(const c0ip_problem* p, int level, int64_t* n_total);
 
 /* y = A_l x: the C0IP matrix of eq. bfc0ip on level l, applied matrix-free
  * through its Kronecker form (Sec. 4, eqs. c0iptensorvp / c0iptensorvp3D).
- * x and y must not overlap. */
+ * x and y must not overlap (no shared byte; else C0IP_EINVAL). */
 c0ip_status c0ip_apply_A(c0ip_problem* p, int level, c0ip_dtype dtype, const void* x, void* y);
 
-/* One step of the additive vertex-patch smoother (Sec. 3):
+/* One step of the handle's vertex-patch smoother (Sec. 3).  Additive:
  *   x <- x + omega * sum_v R_v^T A~_v^{-1} R_v (b - A_l x),
  * with A~_v the separable local matrix of eq. localsolverbila inverted by
- * fast diagonalisation (eq. inverse).  x_is_zero = 1 treats x as 0 on
- * input (no residual is formed; x is output only).  b and x must not
- * overlap. */
+ * fast diagonalisation (eq. inverse); coloured multiplicative: the same
+ * update restricted to one colour's patches, colour after colour, each
+ * with the residual of the current iterate.  x_is_zero = 1 treats x as 0
+ * on input (x is output only).  b and x must not overlap. */
 c0ip_status c0ip_apply_smoother(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b, void* x,
                                 int x_is_zero);
 
@@ -168,6 +181,23 @@ c0ip_status c0ip_vcycle(c0ip_problem* p, c0ip_dtype dtype, const void* b, void* 
  * Returns C0IP_NOT_CONVERGED (x = last iterate) if max_iters is reached. */
 c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const double* b, double* x,
                        c0ip_solve_info* info);
+
+/* Solve A_L x = b by flexible conjugate gradients in float64, preconditioned
+ * by one V-cycle (precision opts.vcycle_dtype) per iteration: the paper's
+ * Krylov method for the symmetric additive smoother (Sec. 5.1).  One
+ * retained direction: z = MG(r), p = z - ((z . q_old) / (p_old . q_old))
+ * p_old (p = z at the first iteration), q = A p, alpha = (r . p) / (p . q),
+ * x += alpha p, r -= alpha q; the flexible form tolerates a preconditioner
+ * that is symmetric only up to rounding (the float32 V-cycle).  Stops when
+ * the recursive residual ||r||_2 <= rtol ||b||_2; opts->restart is not
+ * used.  info (may be NULL): iterations, rel_res_est = ||r|| / ||b||,
+ * rel_res_true = ||b - A x|| / ||b|| recomputed, frac_iters from the
+ * reduction ||r_n|| / ||r_0||, seconds_arnoldi = time outside the V-cycles.
+ * b, x: float64 device vectors of the finest level.  Returns
+ * C0IP_NOT_CONVERGED (x = last iterate) if max_iters is reached, C0IP_ENAN
+ * on a non-finite value (an indefinite preconditioner shows as one). */
+c0ip_status c0ip_solve_fcg(c0ip_problem* p, const c0ip_krylov_opts* opts, const double* b, double* x,
+                           c0ip_solve_info* info);
 
 /* ---- batched solves (many independent 2D systems, one graph per round) ----
  * A batch holds n_problems 2D problems (meshes[i]: any n_cells and degree)

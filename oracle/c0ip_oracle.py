@@ -327,6 +327,10 @@ def patch_blocks(A: sp.csr_matrix, pidx: np.ndarray) -> np.ndarray:
     """Dense blocks A[I_v, I_v] for every patch: A_v = R_v A R_v^T."""
     P, m = pidx.shape
     out = np.empty((P, m, m))
+    if m > 256:  # large blocks (3D, high degree): row then column slices of the CSR matrix
+        for p in range(P):
+            out[p] = A[pidx[p]][:, pidx[p]].toarray()
+        return out
     chunk = max(1, 2_000_000 // (m * m))
     for s in range(0, P, chunk):
         idx = pidx[s:s + chunk]

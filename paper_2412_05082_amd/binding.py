@@ -29,7 +29,7 @@ class MeshDesc(C.Structure):
 class MgOpts(C.Structure):
     _fields_ = [("omega", C.c_double), ("pre_steps", C.c_int), ("post_steps", C.c_int),
                 ("vcycle_dtype", C.c_int), ("coarse_mode", C.c_int), ("scatter_mode", C.c_int),
-                ("tail_levels", C.c_int)]
+                ("tail_levels", C.c_int), ("smoother", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -68,6 +68,7 @@ _SIGS = {
     "c0ip_tuned_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "c0ip_set_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "c0ip_solve": (C.c_int, [C.c_void_p, C.POINTER(KrylovOpts), C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]),
+    "c0ip_solve_fcg": (C.c_int, [C.c_void_p, C.POINTER(KrylovOpts), C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]),
     "c0ip_last_error": (C.c_char_p, []),
     "c0ip_batch_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_int), C.c_int, C.POINTER(MgOpts), C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
@@ -115,12 +116,14 @@ class Problem:
     """Owns a c0ip_problem handle (c0ip_create / c0ip_destroy)."""
 
     def __init__(self, dim, n_cells, degree, gamma=0.0, omega=None, pre_steps=1, post_steps=1,
-                 vcycle_dtype=C0IP_F32, coarse_mode=0, scatter_mode=0, tail_levels=-1, stream=None):
+                 vcycle_dtype=C0IP_F32, coarse_mode=0, scatter_mode=0, tail_levels=-1, smoother=0, stream=None):
+        """smoother: 0 = additive (AVS), 1 = coloured multiplicative (MVS)."""
         lib = load_library()
         if omega is None:
             omega = 0.25 if dim == 2 else 0.1
         self.mesh = MeshDesc(dim, n_cells, degree, gamma)
-        self.mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels)
+        self.mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels,
+                         smoother)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -202,18 +205,29 @@ class Problem:
         _check(st)
         return info.as_dict()
 
+    def solve_fcg(self, b, x, rtol=1e-8, max_iters=500, x0_is_zero=True, raise_on_nonconv=True):
+        """c0ip_solve_fcg: flexible CG preconditioned by the V-cycle."""
+        opts = KrylovOpts(rtol, max_iters, 1, int(bool(x0_is_zero)))
+        info = SolveInfo()
+        st = load_library().c0ip_solve_fcg(self._h, C.byref(opts), self._vec(b, -1, C0IP_F64),
+                                           self._vec(x, -1, C0IP_F64), C.byref(info))
+        if st == -4 and not raise_on_nonconv:
+            return info.as_dict()
+        _check(st)
+        return info.as_dict()
+
 
 class Batch:
     """Owns a c0ip_batch: problems = [(n_cells, degree), ...] (2D), n_rhs per problem."""
 
     def __init__(self, problems, n_rhs, gamma=0.0, omega=0.25, pre_steps=1, post_steps=1, vcycle_dtype=C0IP_F32,
-                 coarse_mode=0, tail_levels=-1, scatter_mode=0, stream=None):
+                 coarse_mode=0, tail_levels=-1, scatter_mode=0, smoother=0, stream=None):
         lib = load_library()
         self.problems = list(problems)
         self.n_rhs = list(n_rhs)
         meshes = (MeshDesc * len(self.problems))(*[MeshDesc(2, N, k, gamma) for N, k in self.problems])
         rhs = (C.c_int * len(self.n_rhs))(*self.n_rhs)
-        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels)
+        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels, smoother)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

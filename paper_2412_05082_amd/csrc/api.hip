@@ -13,6 +13,7 @@
 #include "../../include/c0ip.h"
 #include "internal.h"
 #include "kernels.h"
+#include "krylov_cg.h"
 #include "setup.h"
 
 namespace {
@@ -99,6 +100,9 @@ struct c0ip_problem {
   DevBuf<double> V, w, u, partial, hdev, coef, ydev, r64;
   DevBuf<double> Z64;
   DevBuf<float> Z32;
+  // flexible CG work space
+  DevBuf<double> cg_p, cg_q, cg_z64, cg_sc, cg_partial;
+  DevBuf<float> cg_z32;
   double* hpin = nullptr;  // pinned host staging for the per-step reductions
   ~c0ip_problem() {
     if (hpin) (void)hipHostFree(hpin);
@@ -113,6 +117,8 @@ struct c0ip_problem {
   void smooth(int l, const T* b, T* x, int steps, bool x_is_zero);
   template <typename T>
   void smooth_from(int l, const T* b, T* from, T* x, int steps);
+  template <typename T>
+  void smooth_mvs(int l, const T* b, T* x, T* r, int steps, bool x_is_zero);
   template <typename T>
   void mg_level(int l, const T* b, T* x);
   template <typename T>
@@ -190,6 +196,10 @@ void c0ip_problem::smooth(int l, const T* b, T* x, int steps, bool x_is_zero) {
     if (x_is_zero) check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), x, stream), "fill");
     return;
   }
+  if (mg.smoother == 1) {
+    smooth_mvs<T>(l, b, x, w.r.p, steps, x_is_zero);
+    return;
+  }
   if (mg.scatter_mode == 1) {  // atomic scatter: in place, residual through the level's r
     for (int s = 0; s < steps; ++s) {
       if (s == 0 && x_is_zero) {
@@ -217,7 +227,7 @@ void c0ip_problem::smooth_from(int l, const T* b, T* from, T* x, int steps) {
   LevelWork<T>& w = work<T>(l);
   const int Nl = lv[l]->N;
   const T om = (T)mg.omega;
-  if (mg.scatter_mode == 1) {
+  if (mg.scatter_mode == 1 || mg.smoother == 1) {
     if (from != x) check(hipMemcpyAsync(x, from, sizeof(T) * lv[l]->ntot, hipMemcpyDeviceToDevice, stream), "copy");
     smooth<T>(l, b, x, steps, false);
     return;
@@ -241,6 +251,28 @@ void c0ip_problem::smooth_from(int l, const T* b, T* from, T* x, int steps) {
   }
 }
 
+// `steps` steps of the coloured multiplicative smoother on level l, in
+// place on x: per colour c = 0..7, r = b - A x (r = b for the first colour
+// of a step from x = 0), then x += omega * (local solves of colour c).
+template <typename T>
+void c0ip_problem::smooth_mvs(int l, const T* b, T* x, T* r, int steps, bool x_is_zero) {
+  LevelWork<T>& w = work<T>(l);
+  const int Nl = lv[l]->N;
+  const T om = (T)mg.omega;
+  const int ncol = 1 << (dim + 1);
+  for (int s = 0; s < steps; ++s)
+    for (int c = 0; c < ncol; ++c) {
+      const T* rc = r;
+      if (s == 0 && c == 0 && x_is_zero) {
+        check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), x, stream), "fill");
+        rc = b;
+      } else {
+        check(c0ip::launch_apply<T, T>(dim, k, Nl, w.coef, x, b, r, stream), "residual");
+      }
+      check(c0ip::launch_mvs2d_colour<T>(k, Nl, c, w.eig, rc, x, om, stream), "multiplicative smoother colour");
+    }
+}
+
 // The tail runs levels 0..LT in one launch: LT is the highest level (at
 // most the finest, at most tail_levels - 1) whose vectors and tables fit in
 // the LDS of one workgroup; below level 1 there is nothing to gain.
@@ -249,7 +281,7 @@ int c0ip_problem::tail_level() {
   int& t = tailLT[sizeof(T) == 4 ? 1 : 0];
   if (t != -2) return t;
   t = -1;
-  if (dim != 2 || k > 4 || mg.tail_levels == 0 || mg.scatter_mode != 0) return t;
+  if (dim != 2 || k > 4 || mg.tail_levels == 0 || mg.scatter_mode != 0 || mg.smoother != 0) return t;
   const int lim = c0ip::tail_lds_limit();
   int cap = std::min(L, c0ip::kTailMaxLevels - 1);
   if (mg.tail_levels > 0) cap = std::min(cap, mg.tail_levels - 1);
@@ -362,7 +394,7 @@ void c0ip_problem::mg_level(int l, const T* b, T* x) {
   }
   LevelWork<T>& w = work<T>(l);
   LevelWork<T>& wc = work<T>(l - 1);
-  if (dim == 2 && mg.scatter_mode == 0) {
+  if (dim == 2 && mg.scatter_mode == 0 && mg.smoother == 0) {
     mg_level2d<T>(l, b, x);
     return;
   }
@@ -435,6 +467,50 @@ template int c0ip_internal_variant<float>(c0ip_problem*, int);
 template const double* c0ip_internal_ptab<double>(c0ip_problem*, int);
 template const float* c0ip_internal_ptab<float>(c0ip_problem*, int);
 
+namespace {
+
+// Do the n elements of esz bytes at a and at b share any byte?
+bool overlaps(const void* a, const void* b, int64_t n, size_t esz) {
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b, len = (uintptr_t)n * esz;
+  return pa < pb + len && pb < pa + len;
+}
+
+// One out-of-place smoother step x_out = S(x_in, b) on level l (S(0, b) when
+// x_in is null); r: residual work space of ntot(l) elements, used in 3D and
+// by the atomic scatter.
+template <typename T>
+void smoother_step_on(c0ip_problem* p, int l, const T* b, const T* x_in, T* x_out, T* r) {
+  LevelWork<T>& w = p->work<T>(l);
+  const int Nl = p->lv[l]->N;
+  const T om = (T)p->mg.omega;
+  if (p->mg.smoother == 1) {
+    if (x_in)
+      p->check(hipMemcpyAsync(x_out, x_in, sizeof(T) * p->lv[l]->ntot, hipMemcpyDeviceToDevice, p->stream), "copy");
+    p->smooth_mvs<T>(l, b, x_out, r, 1, x_in == nullptr);
+    return;
+  }
+  if (p->mg.scatter_mode == 1) {
+    if (x_in) {
+      p->check(c0ip::launch_apply2d<T, T>(p->k, Nl, w.coef, x_in, b, r, p->stream), "residual");
+      p->check(hipMemcpyAsync(x_out, x_in, sizeof(T) * p->lv[l]->ntot, hipMemcpyDeviceToDevice, p->stream), "copy");
+    } else {
+      p->check(c0ip::launch_fill_t<T>(p->lv[l]->ntot, T(0), x_out, p->stream), "fill");
+    }
+    p->check(c0ip::launch_patch2d_atomic<T>(p->k, Nl, w.eig, x_in ? r : b, x_out, om, p->stream), "atomic smoother");
+  } else if (!x_in) {
+    p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, b, nullptr, x_out, om, p->stream), "smoother");
+  } else if (p->dim == 2) {
+    p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, x_in, b, x_out, om, p->stream, 1, 0, nullptr,
+                                   w.avs_variant),
+             "fused smoother");
+  } else {
+    p->check(c0ip::launch_apply<T, T>(p->dim, p->k, Nl, w.coef, x_in, b, r, p->stream), "residual");
+    p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, r, x_in, x_out, om, p->stream), "smoother");
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* c0ip_last_error(void) { return g_err.c_str(); }
@@ -456,8 +532,14 @@ c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, vo
     mg.coarse_mode = 0;
     mg.scatter_mode = 0;
     mg.tail_levels = -1;
+    mg.smoother = 0;
   }
   if (!(mg.omega > 0) || !std::isfinite(mg.omega)) return fail(C0IP_EINVAL, "omega must be > 0");
+  if (mg.smoother != 0 && mg.smoother != 1) return fail(C0IP_EINVAL, "smoother must be 0 or 1");
+  if (mg.smoother == 1 && mg.scatter_mode != 0)
+    return fail(C0IP_EINVAL, "the multiplicative smoother takes scatter_mode 0");
+  if (mg.smoother == 1 && mesh->dim != 2)
+    return fail(C0IP_EUNSUPPORTED, "the multiplicative smoother is built for 2D meshes only");
   if (mg.pre_steps < 0 || mg.post_steps < 0 || mg.pre_steps > 16 || mg.post_steps > 16)
     return fail(C0IP_EINVAL, "smoothing steps must be in [0,16]");
   if (mg.vcycle_dtype != C0IP_F64 && mg.vcycle_dtype != C0IP_F32) return fail(C0IP_EINVAL, "bad vcycle_dtype");
@@ -559,8 +641,9 @@ c0ip_status c0ip_apply_A(c0ip_problem* p, int level, c0ip_dtype dtype, const voi
   g_err.clear();
   if (!p || !x || !y) return fail(C0IP_EINVAL, "NULL argument");
   if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
-  if (x == y) return fail(C0IP_EINVAL, "x and y must not overlap");
   const int l = resolve_level(p, level);
+  if (overlaps(x, y, p->ntot(l), dtype == C0IP_F32 ? sizeof(float) : sizeof(double)))
+    return fail(C0IP_EINVAL, "x and y must not overlap");
   try {
     if (dtype == C0IP_F64) {
       p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->lv[l]->N, p->work<double>(l).coef,
@@ -585,8 +668,9 @@ c0ip_status c0ip_apply_smoother(c0ip_problem* p, int level, c0ip_dtype dtype, co
   g_err.clear();
   if (!p || !b || !x) return fail(C0IP_EINVAL, "NULL argument");
   if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
-  if (b == x) return fail(C0IP_EINVAL, "b and x must not overlap");
   const int l = resolve_level(p, level);
+  if (overlaps(b, x, p->ntot(l), dtype == C0IP_F32 ? sizeof(float) : sizeof(double)))
+    return fail(C0IP_EINVAL, "b and x must not overlap");
   try {
     if (dtype == C0IP_F64) {
       p->smooth<double>(l, (const double*)b, (double*)x, 1, x_is_zero != 0);
@@ -607,41 +691,19 @@ c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, con
   g_err.clear();
   if (!p || !b || !x_out) return fail(C0IP_EINVAL, "NULL argument");
   if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
-  if (x_out == b || x_out == x_in) return fail(C0IP_EINVAL, "x_out must not overlap b or x_in");
+  if (dtype != C0IP_F64 && dtype != C0IP_F32) return fail(C0IP_EINVAL, "bad dtype");
   const int l = resolve_level(p, level);
+  const size_t esz = dtype == C0IP_F64 ? sizeof(double) : sizeof(float);
+  if (overlaps(x_out, b, p->ntot(l), esz) || (x_in && overlaps(x_out, x_in, p->ntot(l), esz)))
+    return fail(C0IP_EINVAL, "x_out must not overlap b or x_in");
   try {
-    auto run = [&](auto tag) {
-      using T = decltype(tag);
-      p->prepare<T>(l);
-      LevelWork<T>& w = p->work<T>(l);
-      const int Nl = p->lv[l]->N;
-      const T om = (T)p->mg.omega;
-      const T* bb = (const T*)b;
-      const T* xi = (const T*)x_in;
-      T* xo = (T*)x_out;
-      if (p->mg.scatter_mode == 1) {
-        if (xi) {
-          p->check(c0ip::launch_apply2d<T, T>(p->k, Nl, w.coef, xi, bb, w.r.p, p->stream), "residual");
-          p->check(hipMemcpyAsync(xo, xi, sizeof(T) * p->lv[l]->ntot, hipMemcpyDeviceToDevice, p->stream), "copy");
-        } else {
-          p->check(c0ip::launch_fill_t<T>(p->lv[l]->ntot, T(0), xo, p->stream), "fill");
-        }
-        p->check(c0ip::launch_patch2d_atomic<T>(p->k, Nl, w.eig, xi ? w.r.p : bb, xo, om, p->stream),
-                 "atomic smoother");
-      } else if (!xi) {
-        p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, bb, nullptr, xo, om, p->stream), "smoother");
-      } else if (p->dim == 2) {
-        p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, xi, bb, xo, om, p->stream, 1, 0, nullptr,
-                                       w.avs_variant),
-                 "fused smoother");
-      } else {
-        p->check(c0ip::launch_apply<T, T>(p->dim, p->k, Nl, w.coef, xi, bb, w.r.p, p->stream), "residual");
-        p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, w.r.p, xi, xo, om, p->stream), "smoother");
-      }
-    };
-    if (dtype == C0IP_F64) run(double{});
-    else if (dtype == C0IP_F32) run(float{});
-    else return fail(C0IP_EINVAL, "bad dtype");
+    if (dtype == C0IP_F64) {
+      p->prepare<double>(l);
+      smoother_step_on<double>(p, l, (const double*)b, (const double*)x_in, (double*)x_out, p->work<double>(l).r.p);
+    } else {
+      p->prepare<float>(l);
+      smoother_step_on<float>(p, l, (const float*)b, (const float*)x_in, (float*)x_out, p->work<float>(l).r.p);
+    }
   } catch (const HipFail& h) {
     return hip_fail(h);
   }
@@ -720,7 +782,8 @@ c0ip_status c0ip_tuned_variant(const c0ip_problem* p, int level, c0ip_dtype dtyp
 c0ip_status c0ip_vcycle(c0ip_problem* p, c0ip_dtype dtype, const void* b, void* x) {
   g_err.clear();
   if (!p || !b || !x) return fail(C0IP_EINVAL, "NULL argument");
-  if (b == x) return fail(C0IP_EINVAL, "b and x must not overlap");
+  if (overlaps(b, x, p->ntot(p->L), dtype == C0IP_F32 ? sizeof(float) : sizeof(double)))
+    return fail(C0IP_EINVAL, "b and x must not overlap");
   try {
     if (dtype == C0IP_F64) {
       p->mg_level<double>(p->L, (const double*)b, (double*)x);
@@ -768,7 +831,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   if (!p || !opts || !b || !x) return fail(C0IP_EINVAL, "NULL argument");
   if (!(opts->rtol > 0) || opts->max_iters < 1 || opts->restart < 1 || opts->restart > 64)
     return fail(C0IP_EINVAL, "bad Krylov options (rtol > 0, max_iters >= 1, restart in [1,64])");
-  if (b == x) return fail(C0IP_EINVAL, "b and x must not overlap");
+  if (overlaps(b, x, p->ntot(p->L), sizeof(double))) return fail(C0IP_EINVAL, "b and x must not overlap");
   const int m = opts->restart, Lf = p->L;
   const int64_t n = p->ntot(Lf);
   const bool f32 = p->mg.vcycle_dtype == C0IP_F32;
@@ -930,6 +993,126 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (ef) (void)hipEventDestroy(ef);
+  auto t1 = std::chrono::steady_clock::now();
+  inf.seconds_total = std::chrono::duration<double>(t1 - t0).count();
+  inf.seconds_vcycle = t_vc;
+  inf.seconds_arnoldi = std::max(0.0, inf.seconds_total - t_vc);
+  if (info) *info = inf;
+  return result;
+}
+
+c0ip_status c0ip_solve_fcg(c0ip_problem* p, const c0ip_krylov_opts* opts, const double* b, double* x,
+                           c0ip_solve_info* info) {
+  g_err.clear();
+  if (!p || !opts || !b || !x) return fail(C0IP_EINVAL, "NULL argument");
+  if (!(opts->rtol > 0) || opts->max_iters < 1) return fail(C0IP_EINVAL, "bad Krylov options (rtol > 0, max_iters >= 1)");
+  if (overlaps(b, x, p->ntot(p->L), sizeof(double))) return fail(C0IP_EINVAL, "b and x must not overlap");
+  const int Lf = p->L;
+  const int64_t n = p->ntot(Lf);
+  const bool f32 = p->mg.vcycle_dtype == C0IP_F32;
+  hipStream_t s = p->stream;
+  c0ip_solve_info inf{};
+  auto t0 = std::chrono::steady_clock::now();
+  double t_vc = 0;
+  c0ip_status result = C0IP_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    namespace cg = c0ip::cg;
+    const int nblk = cg::blocks(n);
+    p->r64.alloc(n);
+    p->w.alloc(n);
+    p->cg_p.alloc(n);
+    p->cg_q.alloc(n);
+    p->cg_sc.alloc(cg::kSlots);
+    p->cg_partial.alloc((size_t)2 * nblk);
+    if (f32) {
+      p->cg_z32.alloc(n);
+      for (int l = 0; l <= Lf; ++l) p->prepare<float>(l);
+    } else {
+      p->cg_z64.alloc(n);
+    }
+    if (!p->hpin) p->check(hipHostMalloc((void**)&p->hpin, sizeof(double) * (4 * 64 + 16)), "pinned alloc");
+    p->check(hipEventCreate(&e0), "event");
+    p->check(hipEventCreate(&e1), "event");
+    double* hh = p->hpin;
+    double* sc = p->cg_sc.p;
+    double* r = p->r64.p;
+    const auto& cf64 = p->work<double>(Lf).coef;
+    auto rnorm2 = [&](const double* v) {
+      p->check(cg::launch_dot<double>(n, v, v, p->cg_partial.p, nblk, s), "dot");
+      p->check(cg::launch_reduce(1, nblk, p->cg_partial.p, sc, cg::kRR, 0, s), "reduce");
+      p->check(hipMemcpyAsync(hh, sc + cg::kRR, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+      p->check(hipStreamSynchronize(s), "sync");
+      return hh[0];
+    };
+    // ||b|| over the free DoFs (boundary entries of b are ignored): r = b - A 0
+    p->check(c0ip::launch_fill(n, 0.0, p->w.p, s), "fill");
+    p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, p->w.p, b, r, s), "mask b");
+    const double bnorm = std::sqrt(rnorm2(r));
+    if (!std::isfinite(bnorm)) throw c0ip_status(C0IP_ENAN);
+    if (opts->x0_is_zero)
+      p->check(c0ip::launch_fill(n, 0.0, x, s), "fill");
+    else
+      p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, x, b, r, s), "residual");
+    double rr = opts->x0_is_zero ? bnorm * bnorm : rnorm2(r);
+    const double r0 = std::sqrt(rr);
+    int its = 0;
+    bool converged = bnorm == 0.0 || std::sqrt(rr) <= opts->rtol * bnorm;
+    while (!converged && its < opts->max_iters) {
+      if (!std::isfinite(rr)) throw c0ip_status(C0IP_ENAN);
+      const int first = its == 0;
+      p->check(hipEventRecord(e0, s), "event");
+      if (f32) {
+        LevelWork<float>& wf = p->work<float>(Lf);
+        p->check(c0ip::launch_cast<double, float>(n, r, wf.b.p, s), "cast");
+        p->mg_level<float>(Lf, wf.b.p, p->cg_z32.p);
+      } else {
+        p->mg_level<double>(Lf, r, p->cg_z64.p);
+      }
+      p->check(hipEventRecord(e1, s), "event");
+      // beta = (z . q_old) / (p_old . q_old); p = z - beta p_old
+      if (!first) {
+        if (f32) p->check(cg::launch_dot<float>(n, p->cg_z32.p, p->cg_q.p, p->cg_partial.p, nblk, s), "dot");
+        else p->check(cg::launch_dot<double>(n, p->cg_z64.p, p->cg_q.p, p->cg_partial.p, nblk, s), "dot");
+        p->check(cg::launch_reduce(1, nblk, p->cg_partial.p, sc, cg::kZQ, 1, s), "reduce");
+      }
+      if (f32) p->check(cg::launch_update_p<float>(n, p->cg_z32.p, sc, p->cg_p.p, first, s), "update p");
+      else p->check(cg::launch_update_p<double>(n, p->cg_z64.p, sc, p->cg_p.p, first, s), "update p");
+      // q = A p; alpha = (r . p) / (p . q); x += alpha p; r -= alpha q
+      p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, p->cg_p.p, nullptr, p->cg_q.p, s), "A p");
+      p->check(cg::launch_dot2(n, p->cg_p.p, p->cg_q.p, r, p->cg_partial.p, nblk, s), "dots");
+      p->check(cg::launch_reduce(2, nblk, p->cg_partial.p, sc, cg::kPQ, 2, s), "reduce");
+      p->check(cg::launch_update_xr(n, sc, p->cg_p.p, p->cg_q.p, x, r, p->cg_partial.p, nblk, s), "update x, r");
+      p->check(cg::launch_reduce(1, nblk, p->cg_partial.p, sc, cg::kRR, 0, s), "reduce");
+      p->check(hipMemcpyAsync(hh, sc, cg::kSlots * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+      p->check(hipStreamSynchronize(s), "sync");
+      float ms = 0;
+      p->check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      t_vc += ms * 1e-3;
+      ++its;
+      rr = hh[cg::kRR];
+      if (!std::isfinite(rr) || !std::isfinite(hh[cg::kALPHA])) throw c0ip_status(C0IP_ENAN);
+      converged = std::sqrt(rr) <= opts->rtol * bnorm;
+    }
+    // true residual of the returned x
+    p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, x, b, p->cg_q.p, s), "residual");
+    const double rt = std::sqrt(rnorm2(p->cg_q.p));
+    inf.iterations = its;
+    inf.converged = converged ? 1 : 0;
+    inf.rel_res_est = bnorm > 0 ? std::sqrt(rr) / bnorm : 0.0;
+    inf.rel_res_true = bnorm > 0 ? rt / bnorm : 0.0;
+    const double red = r0 > 0 ? std::sqrt(rr) / r0 : 0.0;
+    inf.frac_iters = (its > 0 && red > 0 && red < 1) ? 8.0 * its / (-std::log10(red)) : 0.0;
+    if (!std::isfinite(rt)) result = fail(C0IP_ENAN, "non-finite residual");
+    else if (!converged) result = fail(C0IP_NOT_CONVERGED, "max_iters reached");
+  } catch (const HipFail& h) {
+    result = hip_fail(h);
+  } catch (c0ip_status st) {
+    (void)hipStreamSynchronize(s);
+    result = fail(st, "non-finite value in the Krylov iteration");
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   auto t1 = std::chrono::steady_clock::now();
   inf.seconds_total = std::chrono::duration<double>(t1 - t0).count();
   inf.seconds_vcycle = t_vc;

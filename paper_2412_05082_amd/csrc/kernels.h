@@ -101,6 +101,12 @@ hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const 
 // (xout initialised by the caller; each patch solved once).
 template <typename T>
 hipError_t launch_patch2d_atomic(int k, int N, const LevelEig<T>& e, const T* r, T* xout, T omega, hipStream_t s);
+// One colour of the coloured multiplicative smoother (2D, 8 colours):
+// x += omega * sum over the colour's patches of R_v^T A~_v^{-1} R_v r, in
+// place (the colour's patches are disjoint and A-orthogonal).
+template <typename T>
+hipError_t launch_mvs2d_colour(int k, int N, int colour, const LevelEig<T>& e, const T* r, T* x, T omega,
+                               hipStream_t s);
 // One fused smoothing step S(x, b) (residual in LDS; x_out must not alias x).
 // variant: tile-size variant (0 = default; see avs2d_variants).  With ec:
 // the step starts from x + P ec instead (ec: coarse vector of the level

@@ -277,6 +277,162 @@ hipError_t patch2d_atomic_k(int N, const LevelEig<T>& e, const T* r, T* xout, T 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ coloured multiplicative
+// One colour of the coloured multiplicative smoother (Sec. 3, Fig. 2):
+//   x <- x + omega * sum_{v of colour c} R_v^T A~_v^{-1} R_v r,   r = b - A x
+// taken after the previous colour.  Colour c = px + 2 py + 4 rb holds the
+// vertices v = (2a + px, 2b + py) in [1, N-1]^2 with (a + b) mod 2 = rb;
+// their patches share no node and no entry of A couples two of them, so
+// each patch is solved once and its correction is added in place with a
+// plain store (no other patch of the colour touches its nodes).  The
+// vertices of a colour are numbered row by row of b; rows alternate
+// between two lengths.
+
+struct ColourRows {
+  int a_lo, a_hi, b_lo, nb;  // lattice ranges of a and b
+  int rb;
+  int cnt0, cnt1;            // patches in rows b_lo + 2i and b_lo + 2i + 1
+  int total;
+};
+
+__host__ __device__ inline int colour_row_count(int a_lo, int a_hi, int b, int rb) {
+  const int af = a_lo + (((rb - a_lo - b) % 2) + 2) % 2;
+  return af <= a_hi ? (a_hi - af) / 2 + 1 : 0;
+}
+
+inline ColourRows colour_rows(int N, int c) {
+  const int px = c & 1, py = (c >> 1) & 1;
+  ColourRows cr;
+  cr.rb = (c >> 2) & 1;
+  cr.a_lo = px == 0 ? 1 : 0;
+  cr.a_hi = (N - 1 - px) / 2;
+  cr.b_lo = py == 0 ? 1 : 0;
+  const int b_hi = (N - 1 - py) / 2;
+  cr.nb = b_hi >= cr.b_lo ? b_hi - cr.b_lo + 1 : 0;
+  cr.cnt0 = colour_row_count(cr.a_lo, cr.a_hi, cr.b_lo, cr.rb);
+  cr.cnt1 = colour_row_count(cr.a_lo, cr.a_hi, cr.b_lo + 1, cr.rb);
+  cr.total = (cr.nb / 2) * (cr.cnt0 + cr.cnt1) + (cr.nb % 2) * cr.cnt0;
+  return cr;
+}
+
+// vertex (vx, vy) of the patch with number q of the colour
+__device__ __forceinline__ void colour_vertex(const ColourRows& cr, int px, int py, int q, int& vx, int& vy) {
+  const int pair = cr.cnt0 + cr.cnt1;
+  const int i = q / pair, rem = q - i * pair;
+  const int b = cr.b_lo + 2 * i + (rem >= cr.cnt0 ? 1 : 0);
+  const int t = rem >= cr.cnt0 ? rem - cr.cnt0 : rem;
+  const int af = cr.a_lo + (((cr.rb - cr.a_lo - b) % 2) + 2) % 2;
+  vx = 2 * (af + 2 * t) + px;
+  vy = 2 * b + py;
+}
+
+template <int K> struct ColourPatches { static constexpr int NPW = kThreads / (2 * K - 1); };
+
+template <typename T, int K>
+__global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restrict__ r, T* __restrict__ x, int N,
+                                                                int n1, ColourRows cr, int px, int py,
+                                                                const T* __restrict__ Qg, const T* __restrict__ lamg,
+                                                                T omega) {
+  constexpr int n = 2 * K - 1, NN = n * n, NPW = ColourPatches<K>::NPW;
+  __shared__ T sA[NPW * NN];
+  __shared__ T sB[NPW * NN];
+  __shared__ T sQ[4 * NN];
+  __shared__ T sLam[4 * n];
+  const int q0 = blockIdx.x * NPW;
+  const int np = min(NPW, cr.total - q0);
+  if (np <= 0) return;
+  // gather r on the patches' nodes (rows of n consecutive nodes)
+  for (int e = threadIdx.x; e < np * NN; e += kThreads) {
+    const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
+    int vx, vy;
+    colour_vertex(cr, px, py, q0 + p, vx, vy);
+    sB[e] = r[(size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c];
+  }
+  for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
+  for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
+  __syncthreads();
+  // forward along x: t[a][c] = sum_c' Qx[c'][c] r[a][c']
+  for (int it = threadIdx.x; it < np * n; it += kThreads) {
+    const int p = it / n, a = it - p * n;
+    int vx, vy;
+    colour_vertex(cr, px, py, q0 + p, vx, vy);
+    const T* qx = sQ + variant(vx, N) * NN;
+    T in[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) in[c] = sB[p * NN + a * n + c];
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int cp = 0; cp < n; ++cp) s += qx[cp * n + c] * in[cp];
+      sA[p * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  // along y: forward with Qy^T, divide by lambda_x + lambda_y, back with Qy
+  for (int it = threadIdx.x; it < np * n; it += kThreads) {
+    const int p = it / n, c = it - p * n;
+    int vx, vy;
+    colour_vertex(cr, px, py, q0 + p, vx, vy);
+    const int ty = variant(vy, N), tx = variant(vx, N);
+    const T* qy = sQ + ty * NN;
+    T col[n], t[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) col[a] = sA[p * NN + a * n + c];
+#pragma unroll
+    for (int ap = 0; ap < n; ++ap) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) s += qy[a * n + ap] * col[a];
+      t[ap] = s / (sLam[tx * n + c] + sLam[ty * n + ap]);
+    }
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int ap = 0; ap < n; ++ap) s += qy[a * n + ap] * t[ap];
+      sB[p * NN + a * n + c] = s;
+    }
+  }
+  __syncthreads();
+  // back along x into sA, then x += omega u on the patches' nodes
+  for (int it = threadIdx.x; it < np * n; it += kThreads) {
+    const int p = it / n, a = it - p * n;
+    int vx, vy;
+    colour_vertex(cr, px, py, q0 + p, vx, vy);
+    const T* qx = sQ + variant(vx, N) * NN;
+    T in[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) in[c] = sB[p * NN + a * n + c];
+#pragma unroll
+    for (int cp = 0; cp < n; ++cp) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < n; ++c) s += qx[cp * n + c] * in[c];
+      sA[p * NN + a * n + cp] = s;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < np * NN; e += kThreads) {
+    const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
+    int vx, vy;
+    colour_vertex(cr, px, py, q0 + p, vx, vy);
+    const size_t g = (size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c;
+    x[g] = x[g] + omega * sA[e];
+  }
+}
+
+template <typename T, int K>
+hipError_t mvs2d_colour_k(int N, int colour, const LevelEig<T>& e, const T* r, T* x, T omega, hipStream_t s) {
+  constexpr int NPW = ColourPatches<K>::NPW;
+  const ColourRows cr = colour_rows(N, colour);
+  if (cr.total <= 0) return hipSuccess;
+  const int nblk = (cr.total + NPW - 1) / NPW;
+  mvs2d_colour_kernel<T, K><<<nblk, kThreads, 0, s>>>(r, x, N, K * N + 1, cr, colour & 1, (colour >> 1) & 1, e.Q,
+                                                     e.lam, omega);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ transfers
 // Restriction b_c = P^T r_f and prolongation x_f += P e_c in one launch each:
 // a workgroup owns TCC x TCC coarse cells, stages its fine (or coarse)
@@ -451,6 +607,14 @@ hipError_t launch_patch2d_atomic(int k, int N, const LevelEig<T>& e, const T* r,
 }
 
 template <typename T>
+hipError_t launch_mvs2d_colour(int k, int N, int colour, const LevelEig<T>& e, const T* r, T* x, T omega,
+                               hipStream_t s) {
+#define CALL(K) mvs2d_colour_k<T, K>(N, colour, e, r, x, omega, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template <typename T>
 hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s, int nsys,
                              int64_t zf, int64_t zc, const int* active) {
 #define CALL(K) restrict2d_k<T, K>(Nc, table, rf, bc, s, nsys, zf, zc, active)
@@ -478,6 +642,10 @@ template hipError_t launch_patch2d_atomic<double>(int, int, const LevelEig<doubl
                                                   double, hipStream_t);
 template hipError_t launch_patch2d_atomic<float>(int, int, const LevelEig<float>&, const float*, float*, float,
                                                  hipStream_t);
+template hipError_t launch_mvs2d_colour<double>(int, int, int, const LevelEig<double>&, const double*, double*,
+                                                double, hipStream_t);
+template hipError_t launch_mvs2d_colour<float>(int, int, int, const LevelEig<float>&, const float*, float*, float,
+                                               hipStream_t);
 template hipError_t launch_patch2d<double>(int, int, const LevelEig<double>&, const double*, const double*,
                                            double*, double, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_patch2d<float>(int, int, const LevelEig<float>&, const float*, const float*, float*,

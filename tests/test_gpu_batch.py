@@ -104,3 +104,57 @@ def test_batch_rejects_3d_and_bad_shapes():
     rhs = (C.c_int * 1)(1)
     h = C.c_void_p()
     assert lib.c0ip_batch_create(meshes, rhs, 1, None, None, C.byref(h)) == -6
+
+
+def _c5_problems():
+    """The batched workload: 16 right-hand sides (seeds 0-15) on 2D Q4
+    256^2 cells, plus 48 problems i = 0..47 with 2^(3 + i mod 5) cells per
+    direction, degree 2 + (i // 5) mod 3, right-hand side seed 1000 + i."""
+    probs, rhs, seeds = [(256, 4)], [16], [list(range(16))]
+    for i in range(48):
+        probs.append((2 ** (3 + i % 5), 2 + (i // 5) % 3))
+        rhs.append(1)
+        seeds.append([1000 + i])
+    return probs, rhs, seeds
+
+
+@pytest.mark.timeout(600)
+def test_c5_workload_true_residuals_from_oracle():
+    """The full batched workload (64 systems, 18.7 M DoFs) in one batch with
+    the float32 V-cycle: every system's solution has an oracle residual
+    ||b - A x|| <= 1.05e-8 ||b||, or at most twice the rounding floor
+    eps ||(|A| |x|)|| / ||b|| of evaluating b - A x in float64 where that
+    floor is above 5e-9 (A applied by the oracle, assembled per problem or
+    in row blocks for the 1,050,625-DoF problem)."""
+    say("C5 workload, oracle residuals")
+    probs, rhs, seeds = _c5_problems()
+    bs = [torch.from_numpy(np.stack([seeded_vector(2, k, N, sd) for sd in sl])).cuda()
+          for (N, k), sl in zip(probs, seeds)]
+    bt = P.Batch(probs, rhs, omega=0.25, vcycle_dtype=P.C0IP_F32)
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = bt.solve(bs, xs, rtol=1e-8, restart=50)
+    torch.cuda.synchronize()
+    assert all(inf["converged"] == 1 for inf in infos)
+    worst = 0.0
+    cache = {}
+    eps = np.finfo(np.float64).eps
+    for i, (N, k) in enumerate(probs):
+        bh, xh = host(bs[i]), host(xs[i])
+        if N >= 256:
+            R = bh - O.apply_blocked(2, k, N, xh.T).T
+            F = O.apply_blocked(2, k, N, np.abs(xh.T), absolute=True).T
+        else:
+            if (N, k) not in cache:
+                cache[(N, k)] = O.assemble(2, k, N)
+            A = cache[(N, k)]
+            R = bh - (A @ xh.T).T
+            F = (abs(A) @ np.abs(xh.T)).T
+        for q in range(bh.shape[0]):
+            nb = np.linalg.norm(bh[q])
+            rel, floor = np.linalg.norm(R[q]) / nb, eps * np.linalg.norm(F[q]) / nb
+            worst = max(worst, rel / max(1.05e-8, 2 * floor if floor > 5e-9 else 0.0))
+            if i == 0 or q == 0 and i % 16 == 1:
+                say(f"  system {i}/{q} ({N}^2, Q{k}): oracle residual {rel:.3e}, floor {floor:.3e}, "
+                    f"library rel_res_true {infos[sum(rhs[:i]) + q]['rel_res_true']:.3e}")
+            assert rel <= max(1.05e-8, 2 * floor if floor > 5e-9 else 0.0), (i, q, rel, floor)
+    say(f"  worst residual / bar {worst:.3f} over {len(infos)} systems")

@@ -1,12 +1,13 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances: float64 results within 1e-12 relative l2 of the oracle, or
-2 kappa(A~_v) eps where the patch matrices are worse conditioned (k >= 6:
-two correct float64 local solves differ by up to ~kappa eps);
-float32 operator applies within 1e-5 and float32 smoother applies within
-max(1e-5, 0.05 kappa eps32) relative l2 of the float64 oracle (1e-5 for
-k <= 4; above, the float32 residual's rounding, amplified by the local
-solve's conditioning, sets the limit).  Sizes span several tiles and ragged last tiles; the full-size
+Tolerances (tests/gpu_util.py): float64 results within 1e-12 relative l2
+of the oracle, or 2 kappa(A~_v) eps where the patch matrices are worse
+conditioned (k >= 6: two correct float64 local solves differ by up to
+~kappa eps); float64 V-cycles within (L (pre + post) + 1) times that;
+float32 operator applies and S(0, b) within 1e-5; float32 S(x, b) within
+1e-5 or twice the floor that a float32 residual with exact local solves
+reaches on the same input (above 1e-5 from k = 4 on); float32 V-cycles
+within 1e-5 or twice the oracle's own float32 V-cycle error.  Sizes span several tiles and ragged last tiles; the full-size
 workloads (2D Q3 512^2 and the degree sweep) are checked on sampled
 outputs computed by the windowed oracle.
 """
@@ -16,7 +17,8 @@ import torch
 
 import oracle as O
 import paper_2412_05082_amd as P
-from tests.gpu_util import dev, fp32_tol, fp64_tol, host, oracle_ops, rel_l2, say, vectors
+from tests.gpu_util import (check, dev, fp32_tol, fp32_vcycle_tol, fp64_tol, fp64_vcycle_tol, host, oracle_ops,
+                            rel_l2, say, vectors)
 
 pytestmark = pytest.mark.gpu
 
@@ -81,7 +83,7 @@ def test_smoother_f64_matches_oracle(dim, k, N, x_is_zero):
     xd = dev(x)
     pb.apply_smoother(dev(b), xd, x_is_zero=x_is_zero)
     torch.cuda.synchronize()
-    assert rel_l2(host(xd), ref) <= fp64_tol(dim, k, N)
+    check("S f64", rel_l2(host(xd), ref), fp64_tol(dim, k, N))
 
 
 @pytest.mark.parametrize("dim,k,N", [(2, 2, 32), (2, 3, 32), (2, 4, 16), (2, 5, 8), (2, 6, 8), (2, 7, 8)])
@@ -95,12 +97,12 @@ def test_smoother_f32_matches_oracle(dim, k, N):
     xd = dev(x32)
     pb.apply_smoother(dev(b32), xd)
     torch.cuda.synchronize()
-    assert rel_l2(host(xd), ref) <= fp32_tol(dim, k, N)
+    check("S(x,b) f32", rel_l2(host(xd), ref), fp32_tol(dim, k, N))
     x0 = torch.zeros(x.size, dtype=torch.float32, device="cuda")
     pb.apply_smoother(dev(b32), x0, x_is_zero=True)
     ref0 = O.avs_apply(A, blocks, pidx, None, b32.astype(np.float64), 0.25, 1, x_is_zero=True)
     torch.cuda.synchronize()
-    assert rel_l2(host(x0), ref0) <= 1e-5
+    check("S(0,b) f32", rel_l2(host(x0), ref0), 1e-5)
 
 
 @pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 5, 8), (2, 7, 4), (2, 2, 64), (2, 3, 64),
@@ -114,7 +116,7 @@ def test_vcycle_f64_matches_oracle(dim, k, N):
     xd = torch.empty(b.size, dtype=torch.float64, device="cuda")
     pb.vcycle(dev(b), xd)
     torch.cuda.synchronize()
-    assert rel_l2(host(xd), ref) <= 10 * fp64_tol(dim, k, N)
+    check("vcycle f64", rel_l2(host(xd), ref), fp64_vcycle_tol(dim, k, N))
 
 
 @pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 3, 64), (2, 4, 32)])
@@ -128,7 +130,7 @@ def test_vcycle_f32_matches_oracle(dim, k, N):
     xd = torch.empty(b.size, dtype=torch.float32, device="cuda")
     pb.vcycle(dev(b32), xd)
     torch.cuda.synchronize()
-    assert rel_l2(host(xd), ref) <= 1e-4
+    check("vcycle f32", rel_l2(host(xd), ref), fp32_vcycle_tol(dim, k, N))
 
 
 @pytest.mark.parametrize("k,N", [(2, 16), (3, 16)])
@@ -214,6 +216,64 @@ def test_full_size_sampled_parity(k, N):
         assert np.all(yh[bd] == 0) and np.all(sh[bd] == 0)
 
 
+@pytest.mark.parametrize("k,N", [(3, 512), (2, 512), (4, 512), (7, 256)])
+def test_full_size_f32_smoother_variants_sampled(k, N):
+    """The float32 fused smoother step at the bench's full sizes, in every
+    compiled tile variant (the autotuner picks among them for the bench and
+    the mixed-precision solve) and in the variant the autotuner picked, at
+    sampled DoFs against the windowed oracle on the float32-rounded inputs."""
+    dim = 2
+    say("full size f32 variants", k, N)
+    x, b = vectors(dim, k, N)
+    x, b = x.astype(np.float32), b.astype(np.float32)
+    nodes = _sample_nodes(dim, k, N, 16, 5)
+    sa = O.avs_nodes_windowed(dim, k, N, x.astype(np.float64), b.astype(np.float64), 0.25, nodes)
+    scale = np.abs(sa).max()
+    bar = fp32_tol(dim, k, N)
+    pb = _problem(dim, k, N, omega=0.25)
+    xd, bd = dev(x), dev(b)
+    variants = []
+    for v in range(3):
+        try:
+            pb.set_variant(v, dtype=P.C0IP_F32)
+        except P.C0ipError:
+            break
+        variants.append(v)
+    pb.autotune()
+    tuned = pb.tuned_variant(dtype=P.C0IP_F32)
+    say("  tuned f32 variant", tuned)
+    for v in variants + ["tuned"]:
+        pb.set_variant(tuned if v == "tuned" else v, dtype=P.C0IP_F32)
+        xo = torch.empty(x.size, dtype=torch.float32, device="cuda")
+        pb.smoother_step(bd, xd, xo)
+        torch.cuda.synchronize()
+        sh = host(xo)
+        check(f"variant {v}", np.abs(sh[nodes] - sa).max() / scale, bar)
+        assert np.isfinite(sh).all()
+
+
+@pytest.mark.parametrize("dim,k,N", [(2, 3, 64), (2, 5, 16), (3, 3, 8), (3, 2, 32)])
+def test_owner_computes_is_deterministic(dim, k, N):
+    """Owner computes writes every DoF once in a fixed order: two runs of
+    the smoother step and of the V-cycle (both precisions) give bitwise
+    equal results."""
+    say("determinism", dim, k, N)
+    x, b = vectors(dim, k, N)
+    pb = _problem(dim, k, N)
+    for tdt in (torch.float64, torch.float32):
+        xd, bd = dev(x, tdt), dev(b, tdt)
+        outs = []
+        for rep in range(2):
+            xo = torch.empty_like(xd)
+            pb.smoother_step(bd, xd, xo)
+            z = torch.empty_like(xd)
+            pb.vcycle(bd, z)
+            torch.cuda.synchronize()
+            outs.append((xo.cpu().numpy(), z.cpu().numpy()))
+        assert np.array_equal(outs[0][0], outs[1][0])
+        assert np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_abi_rejects_bad_arguments():
     say("abi errors")
     for kw in [dict(dim=4, N=8, k=3), dict(dim=2, N=6, k=3), dict(dim=3, N=40, k=2), dict(dim=2, N=8, k=1),
@@ -288,34 +348,43 @@ def test_vcycle_smoothing_steps(pre, post):
     xd = torch.empty(b.size, dtype=torch.float64, device="cuda")
     pb.vcycle(dev(b), xd)
     torch.cuda.synchronize()
-    assert rel_l2(host(xd), ref) <= 10 * fp64_tol(dim, k, N)
+    check("vcycle f64 steps", rel_l2(host(xd), ref), fp64_vcycle_tol(dim, k, N, pre, post))
 
 
-@pytest.mark.parametrize("k,N", [(2, 64), (3, 32), (4, 16), (5, 8), (7, 8)])
-def test_every_fused_tile_variant_and_autotune(k, N):
+@pytest.mark.parametrize("k,N", [(2, 64), (3, 64), (3, 32), (4, 16), (4, 32), (5, 8), (5, 16), (6, 8), (7, 8)])
+@pytest.mark.parametrize("dtype", [P.C0IP_F64, P.C0IP_F32])
+def test_every_fused_tile_variant_and_autotune(k, N, dtype):
     """Each compiled tile size of the fused smoother gives the oracle's
-    S(x, b); the autotuner picks one of them."""
+    S(x, b) in both precisions (meshes with several tiles and a ragged last
+    tile for every size); the autotuner picks one of them, and the step
+    with the variant it picked is checked again."""
     dim = 2
-    say("fused variants", k, N)
+    say("fused variants", k, N, dtype)
     A, blocks, pidx = oracle_ops(dim, k, N)
     x, b = vectors(dim, k, N)
+    tdt = torch.float64 if dtype == P.C0IP_F64 else torch.float32
+    if dtype == P.C0IP_F32:
+        x, b = x.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
+        bar = fp32_tol(dim, k, N)
+    else:
+        bar = fp64_tol(dim, k, N)
     ref = O.avs_apply(A, blocks, pidx, x, b, 0.25, 1)
     pb = _problem(dim, k, N, omega=0.25)
     nvar = 0
     for v in range(3):
         try:
-            pb.set_variant(v, dtype=P.C0IP_F64)
+            pb.set_variant(v, dtype=dtype)
         except P.C0ipError:
             break
         nvar += 1
-        xo = torch.empty(x.size, dtype=torch.float64, device="cuda")
-        pb.smoother_step(dev(b), dev(x), xo)
+        xo = torch.empty(x.size, dtype=tdt, device="cuda")
+        pb.smoother_step(dev(b, tdt), dev(x, tdt), xo)
         torch.cuda.synchronize()
-        assert rel_l2(host(xo), ref) <= fp64_tol(dim, k, N), v
+        check(f"variant {v}", rel_l2(host(xo), ref), bar)
     assert nvar >= 2
     pb.autotune()
-    assert 0 <= pb.tuned_variant(dtype=P.C0IP_F64) < nvar
-    xo = torch.empty(x.size, dtype=torch.float64, device="cuda")
-    pb.smoother_step(dev(b), dev(x), xo)
+    assert 0 <= pb.tuned_variant(dtype=dtype) < nvar
+    xo = torch.empty(x.size, dtype=tdt, device="cuda")
+    pb.smoother_step(dev(b, tdt), dev(x, tdt), xo)
     torch.cuda.synchronize()
-    assert rel_l2(host(xo), ref) <= fp64_tol(dim, k, N)
+    check("autotuned", rel_l2(host(xo), ref), bar)

@@ -2,8 +2,7 @@
 vectors in LDS) against the oracle's V-cycle, and against the same problem
 with the tail switched off, in both precisions, for meshes whose whole
 hierarchy fits in the tail and for meshes where the tiled levels hand over
-to it.  Tolerances as for the V-cycle parity tests: 10x the float64
-smoother bound, 1e-4 for the float32 V-cycle.
+to it.  Tolerances as for the V-cycle parity tests (tests/gpu_util.py).
 """
 import numpy as np
 import pytest
@@ -11,7 +10,7 @@ import torch
 
 import oracle as O
 import paper_2412_05082_amd as P
-from tests.gpu_util import dev, fp64_tol, host, rel_l2, say, vectors
+from tests.gpu_util import check, dev, fp32_vcycle_tol, fp64_tol, fp64_vcycle_tol, host, rel_l2, say, vectors
 
 pytestmark = pytest.mark.gpu
 
@@ -37,12 +36,12 @@ def test_tail_vcycle_matches_oracle(k, N, dtype):
     if dtype == P.C0IP_F32:
         b = b.astype(np.float32)
     ref = O.Hierarchy(2, k, N, omega=0.25).vcycle(b.astype(np.float64))
-    tol = 10 * fp64_tol(2, k, N) if dtype == P.C0IP_F64 else 1e-4
+    tol = fp64_vcycle_tol(2, k, N) if dtype == P.C0IP_F64 else fp32_vcycle_tol(2, k, N)
     outs = {t: _vcycle(k, N, dtype, b, tail_levels=t) for t in (-1, 0, 2, 3)}
     for t, x in outs.items():
-        assert rel_l2(x, ref) <= tol, t
+        check(f"tail {t}", rel_l2(x, ref), tol)
     # tail on and off agree with each other to rounding
-    assert rel_l2(outs[-1], outs[0]) <= tol
+    check("tail on/off", rel_l2(outs[-1], outs[0]), tol)
 
 
 @pytest.mark.parametrize("pre,post,coarse", [(0, 1, 0), (2, 2, 0), (1, 1, 1), (3, 0, 0), (0, 0, 0)])
@@ -54,7 +53,7 @@ def test_tail_smoothing_steps_and_coarse_modes(pre, post, coarse, N):
     H = O.Hierarchy(2, k, N, omega=0.25, pre=pre, post=post, coarse="cholesky" if coarse == 0 else "smoother")
     ref = H.vcycle(b)
     x = _vcycle(k, N, P.C0IP_F64, b, pre_steps=pre, post_steps=post, coarse_mode=coarse)
-    assert rel_l2(x, ref) <= 10 * fp64_tol(2, k, N)
+    check("tail steps", rel_l2(x, ref), fp64_vcycle_tol(2, k, N, pre, post))
 
 
 def test_tail_inside_solve():
