@@ -159,6 +159,22 @@ c0ip_status c0ip_apply_smoother(c0ip_problem* p, int level, c0ip_dtype dtype, co
 c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b, const void* x_in,
                                void* x_out);
 
+/* The step of c0ip_smoother_step for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, same kernels and result, and no
+ * allocation of any kind during the call.  Where the step needs a residual
+ * buffer (3D meshes, and scatter_mode 1, when x_in != NULL) it uses a fixed
+ * work space of 64 MiB compiled into the library, one copy per GPU (held
+ * until the process ends), instead of the handle's: a level whose residual
+ * needs more (num_dofs x element size > 64 MiB) is rejected with
+ * C0IP_EINVAL.  A float32 call needs the handle's float32 tables (created
+ * with vcycle_dtype = C0IP_F32, or set up by an earlier float32 call of
+ * another entry point), else C0IP_EINVAL.  All calls on one GPU share that
+ * work space and it keeps the last call's contents: calls that overlap in
+ * time on one GPU (several streams, handles or threads) race. */
+c0ip_status c0ip_smoother_step_noalloc(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b,
+                                       const void* x_in, void* x_out);
+
 /* Autotuner: for every level (and each precision the handle has set up),
  * time each compiled tile-size variant of the 2D fused smoother kernel
  * (reps launches after one warm-up, on the handle's stream and work space)

@@ -64,6 +64,7 @@ _SIGS = {
     "c0ip_apply_smoother": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "c0ip_vcycle": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "c0ip_smoother_step": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "c0ip_smoother_step_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "c0ip_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "c0ip_tuned_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "c0ip_set_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
@@ -190,6 +191,14 @@ class Problem:
         xi = None if x_in is None else self._vec(x_in, level, d)
         _check(load_library().c0ip_smoother_step(self._h, level, d, self._vec(b, level, d), xi,
                                                  self._vec(x_out, level, d)))
+
+    def smoother_step_noalloc(self, b, x_in, x_out, level=-1):
+        """c0ip_smoother_step_noalloc: x_out = S(x_in, b) with no allocation
+        (fixed per-GPU work space; see include/c0ip.h)."""
+        d = _dt(b)
+        xi = None if x_in is None else self._vec(x_in, level, d)
+        _check(load_library().c0ip_smoother_step_noalloc(self._h, level, d, self._vec(b, level, d), xi,
+                                                         self._vec(x_out, level, d)))
 
     def vcycle(self, b, x):
         d = _dt(b)

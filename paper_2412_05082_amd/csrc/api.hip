@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -93,6 +94,7 @@ struct c0ip_problem {
   double gamma = 0;
   c0ip_mg_opts mg{};
   hipStream_t stream = nullptr;
+  int device = 0;  // device current at creation
   std::vector<std::unique_ptr<Level>> lv;
   std::vector<double> ptab;  // prolongation table (float64 host copy)
   DevBuf<double> A0inv;
@@ -467,7 +469,46 @@ template int c0ip_internal_variant<float>(c0ip_problem*, int);
 template const double* c0ip_internal_ptab<double>(c0ip_problem*, int);
 template const float* c0ip_internal_ptab<float>(c0ip_problem*, int);
 
+// Work space of c0ip_smoother_step_noalloc: a fixed device array, one copy
+// per GPU (each GPU holds it until the process ends).  Host code never uses
+// its name as an address: c0ip_create looks up the device address once per
+// device (with that device current) and keeps it in g_scratch_addr.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+hipError_t g_scratch_status[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Once per device, with that device current: the device address of scratch.
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_done[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_status[device] = e;
+  g_scratch_addr[device] = e == hipSuccess ? ptr : nullptr;
+  if (e != hipSuccess) (void)hipGetLastError();
+  g_scratch_done[device] = true;
+}
+
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_addr[device];
+}
+
+std::string scratch_error(int device) {
+  if (device < 0 || device >= kMaxDevices) return "device index out of range";
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[device]) return "not set up";
+  return hipGetErrorString(g_scratch_status[device]);
+}
 
 // Do the n elements of esz bytes at a and at b share any byte?
 bool overlaps(const void* a, const void* b, int64_t n, size_t esz) {
@@ -555,6 +596,11 @@ c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, vo
   p->gamma = mesh->gamma > 0 ? mesh->gamma : (double)(p->k * (p->k + 1));
   p->mg = mg;
   p->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(C0IP_EHIP, "hipGetDevice failed");
+  }
+  scratch_setup(p->device);
   int L = 0;
   while ((2 << L) < p->N) ++L;
   p->L = L;
@@ -704,6 +750,44 @@ c0ip_status c0ip_smoother_step(c0ip_problem* p, int level, c0ip_dtype dtype, con
       p->prepare<float>(l);
       smoother_step_on<float>(p, l, (const float*)b, (const float*)x_in, (float*)x_out, p->work<float>(l).r.p);
     }
+  } catch (const HipFail& h) {
+    return hip_fail(h);
+  }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_smoother_step_noalloc(c0ip_problem* p, int level, c0ip_dtype dtype, const void* b,
+                                       const void* x_in, void* x_out) {
+  g_err.clear();
+  if (!p || !b || !x_out) return fail(C0IP_EINVAL, "NULL argument");
+  if (level < -1 || level > p->L) return fail(C0IP_EINVAL, "level out of range");
+  if (dtype != C0IP_F64 && dtype != C0IP_F32) return fail(C0IP_EINVAL, "bad dtype");
+  const int l = resolve_level(p, level);
+  const size_t esz = dtype == C0IP_F64 ? sizeof(double) : sizeof(float);
+  if (overlaps(x_out, b, p->ntot(l), esz) || (x_in && overlaps(x_out, x_in, p->ntot(l), esz)))
+    return fail(C0IP_EINVAL, "x_out must not overlap b or x_in");
+  // the tables of this precision must exist already: setting them up allocates
+  const bool ready = dtype == C0IP_F64 ? p->work<double>(l).ready : p->work<float>(l).ready;
+  if (!ready)
+    return fail(C0IP_EINVAL, "float32 tables are set up at creation only with vcycle_dtype = C0IP_F32 "
+                             "(or by an earlier float32 call of another entry point)");
+  // the residual goes through the work space in 3D, with the atomic scatter
+  // and with the multiplicative smoother (after its first colour, also from 0)
+  const bool needs_r = p->mg.smoother == 1 || (x_in && (p->dim == 3 || p->mg.scatter_mode == 1));
+  void* r = nullptr;
+  if (needs_r) {
+    if ((size_t)p->ntot(l) * esz > kNoAllocScratchBytes)
+      return fail(C0IP_EINVAL, "level has " + std::to_string(p->ntot(l)) + " DoFs: the residual needs " +
+                                   std::to_string((size_t)p->ntot(l) * esz) + " bytes, the fixed work space of " +
+                                   "c0ip_smoother_step_noalloc holds " + std::to_string(kNoAllocScratchBytes));
+    r = scratch_address(p->device);
+    if (!r) return fail(C0IP_EHIP, "the fixed work space has no device address on this GPU: " + scratch_error(p->device));
+  }
+  try {
+    if (dtype == C0IP_F64)
+      smoother_step_on<double>(p, l, (const double*)b, (const double*)x_in, (double*)x_out, (double*)r);
+    else
+      smoother_step_on<float>(p, l, (const float*)b, (const float*)x_in, (float*)x_out, (float*)r);
   } catch (const HipFail& h) {
     return hip_fail(h);
   }
