@@ -40,9 +40,12 @@ def parse():
     ap.add_argument("--reps", type=int, default=30, help="kernel timing repetitions")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-N", type=int, default=128, help="cells per direction of the oracle sample")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the multiplicative-smoother, flexible-CG, omega 0.7 and 16^2 legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-problem workload")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D Q3 128^3 kernel rates")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 2D degree sweep Q2..Q7")
+    ap.add_argument("--no-3d-sweep", action="store_true", help="skip the 3D mixed-precision sweep Q2..Q4")
     ap.add_argument("--only", default=None,
                     choices=["matvec_f64", "smoother_f64", "matvec_f32", "smoother_f32", "copy_f64"],
                     help="run only this kernel's timing loop (for counter collection) and print its ms")
@@ -125,17 +128,32 @@ def time_kernel(fn, sets, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(k, N, omega):
-    """The oracle (plain NumPy/SciPy, float64, dense LU patch solves) solving
-    the same problem class at a smaller size: DoFs solved per second."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(k, N, omega, full_N=512):
+    """The oracle (plain NumPy/SciPy, float64, dense LU patch solves) on the
+    host: its MG-FGMRES solve of the same problem class at N x N cells
+    (DoFs solved per second: the reported value), plus its CSR mat-vec on
+    one core at the full size (2D Q3 512^2) and its additive smoother step
+    (CSR residual + stacked dense LU patch solves, all cores) at N x N."""
     import numpy as np
+    import scipy
 
     import oracle as O
     from paper_2412_05082_amd.inputs import seeded_vector
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     dim = 2
     b = seeded_vector(dim, k, N, 0)
@@ -145,9 +163,42 @@ def cpu_baseline(k, N, omega):
     x, info = O.fgmres(A, b, H.vcycle, rtol=1e-8, restart=50)
     dt = time.perf_counter() - t0
     n = b.size
+    # smoother step at N x N
+    xs = seeded_vector(dim, k, N, 1)
+    At = O.assemble(dim, k, N, bulk="diag")
+    pidx = O.patch_indices(dim, k, N)
+    blocks = O.patch_blocks(At, pidx)
+    t1 = time.perf_counter()
+    O.avs_apply(A, blocks, pidx, xs, b, omega, 1)
+    t_sm = time.perf_counter() - t1
+    del At, blocks, H
+    # CSR mat-vec at the full size, one core
+    Af = O.assemble(dim, k, full_N)
+    xf = seeded_vector(dim, k, full_N, 1)
+    reps = 5
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t2 = time.perf_counter()
+            for _ in range(reps):
+                Af @ xf
+            t_mv = (time.perf_counter() - t2) / reps
+    else:
+        t2 = time.perf_counter()
+        for _ in range(reps):
+            Af @ xf
+        t_mv = (time.perf_counter() - t2) / reps
+    nf = xf.size
     return {"value": n / dt, "unit": "DoFs/s", "cores": int(threads), "kind": "oracle",
             "sample": f"oracle FGMRES(50)+float64 V-cycle solve to 1e-8, 2D Q{k} {N}x{N} cells ({n} DoFs), "
-                      f"{info['iterations']} its, {dt:.2f} s, setup excluded"}
+                      f"{info['iterations']} its, {dt:.2f} s, setup excluded",
+            "cpu_model": _cpu_model(), "host_threads": os.cpu_count(),
+            "numpy": np.__version__, "scipy": scipy.__version__,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "csr_matvec_full_size": {"dofs": nf, "nnz": int(Af.nnz), "cores": 1, "seconds": t_mv,
+                                     "dofs_per_s": nf / t_mv,
+                                     "workload": f"2D Q{k} {full_N}x{full_N} cells, SciPy CSR SpMV"},
+            "avs_smoother_step": {"dofs": n, "cores": int(threads), "seconds": t_sm, "dofs_per_s": n / t_sm,
+                                  "workload": f"2D Q{k} {N}x{N} cells, CSR residual + dense LU patch solves"}}
 
 
 def bench_3d(args, torch, P):
@@ -163,12 +214,12 @@ def bench_3d(args, torch, P):
     pb = P.Problem(dim, N, k, omega=0.1, vcycle_dtype=P.C0IP_F32)
     x = torch.from_numpy(xn).to(dev)
     b = torch.from_numpy(bn).to(dev)
-    sets = [(x, torch.zeros(n, dtype=torch.float64, device=dev), b) for _ in range(2)]
+    sets = [(x.clone(), torch.zeros(n, dtype=torch.float64, device=dev), b.clone()) for _ in range(2)]
     reps = max(3, args.reps // 5)
     ms_mv = time_kernel(lambda s: pb.apply_A(s[0], s[1]), sets, reps, torch)
     ms_sm = time_kernel(lambda s: pb.smoother_step(s[2], s[0], s[1]), sets, reps, torch)
     x32, b32 = x.float(), b.float()
-    sets32 = [(x32, torch.zeros(n, dtype=torch.float32, device=dev), b32) for _ in range(2)]
+    sets32 = [(x32.clone(), torch.zeros(n, dtype=torch.float32, device=dev), b32.clone()) for _ in range(2)]
     ms_mv32 = time_kernel(lambda s: pb.apply_A(s[0], s[1]), sets32, reps, torch)
     ms_sm32 = time_kernel(lambda s: pb.smoother_step(s[2], s[0], s[1]), sets32, reps, torch)
     del sets, sets32, x32, b32
@@ -196,6 +247,94 @@ def bench_3d(args, torch, P):
     for name, ms, byt in [("matvec_f64", ms_mv, 16), ("smoother_f64", ms_sm, 24), ("matvec_f32", ms_mv32, 8),
                           ("smoother_f32", ms_sm32, 12)]:
         out[name] = {"ms": ms, "dofs_per_s": n / (ms * 1e-3), "alg_GBs": byt * n / (ms * 1e-3) / 1e9}
+    return out
+
+
+def timed_solve(fn, torch, reps=3):
+    """Median wall time of reps calls of fn() (after one warm-up) and the last info."""
+    fn()
+    torch.cuda.synchronize()
+    ts, info = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        info = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    return ts[len(ts) // 2], info
+
+
+def bench_extra(args, torch, P, b, x_np):
+    """On the 2D Q3 512^2 workload: the coloured multiplicative smoother
+    (step rate, and the MG-FGMRES solve it preconditions, omega = 1), the
+    flexible-CG solve with the additive V-cycle (1 and 2 smoothing steps),
+    the literal omega = 0.7 additive solve (expected not to converge), and
+    the small 2D Q2 16^2 workload (operator, smoother step and solve in us)."""
+    dev = b.device
+    n = b.numel()
+    out = {}
+    # --- coloured multiplicative smoother: step rates and solves
+    pm = P.Problem(2, args.N, args.k, omega=1.0, smoother=1, vcycle_dtype=P.C0IP_F32)
+    nsets = max(4, int(1.2e9 // (3 * 8 * n)) + 1)
+    sets = [(torch.from_numpy(x_np).to(dev), torch.empty(n, dtype=torch.float64, device=dev), b.clone())
+            for _ in range(nsets)]
+    reps = max(5, args.reps // 3)
+    ms64 = time_kernel(lambda st: pm.smoother_step(st[2], st[0], st[1]), sets, reps, torch)
+    b32 = b.float()
+    sets = [(st[0].float(), torch.empty(n, dtype=torch.float32, device=dev), b32.clone()) for st in sets]
+    ms32 = time_kernel(lambda st: pm.smoother_step(st[2], st[0], st[1]), sets, reps, torch)
+    del sets
+    mvs = {"omega": 1.0, "colours": 8,
+           "step_f64": {"ms": ms64, "dofs_per_s": n / (ms64 * 1e-3)},
+           "step_f32": {"ms": ms32, "dofs_per_s": n / (ms32 * 1e-3)}}
+    pm.close()
+    for name, dt in (("solve_f32_vcycle", P.C0IP_F32), ("solve_f64_vcycle", P.C0IP_F64)):
+        pb = P.Problem(2, args.N, args.k, omega=1.0, smoother=1, vcycle_dtype=dt)
+        x = torch.zeros_like(b)
+        sec, info = timed_solve(lambda: pb.solve(b, x), torch)
+        mvs[name] = {"seconds": sec, "iterations": info["iterations"], "frac_iters": info["frac_iters"],
+                     "rel_res_true": info["rel_res_true"], "dofs_per_s": n / sec,
+                     "seconds_vcycle": info["seconds_vcycle"]}
+        pb.close()
+    out["mvs_2d_q3_512"] = mvs
+    # --- flexible CG with the additive V-cycle (omega 1/4), 1 and 2 smoothing steps
+    fcg = {}
+    for steps in (1, 2):
+        for name, dt in (("f32_vcycle", P.C0IP_F32), ("f64_vcycle", P.C0IP_F64)):
+            pb = P.Problem(2, args.N, args.k, omega=args.omega, pre_steps=steps, post_steps=steps, vcycle_dtype=dt)
+            x = torch.zeros_like(b)
+            sec, info = timed_solve(lambda: pb.solve_fcg(b, x), torch)
+            fcg[f"avs{steps}_{name}"] = {"seconds": sec, "iterations": info["iterations"],
+                                        "frac_iters": info["frac_iters"], "rel_res_true": info["rel_res_true"],
+                                        "dofs_per_s": n / sec, "seconds_vcycle": info["seconds_vcycle"]}
+            pb.close()
+    out["fcg_2d_q3_512"] = fcg
+    # --- the literal damping 0.7 with the additive smoother (2D stability bound is 1/4)
+    om7 = {}
+    for name, dt in (("f32_vcycle", P.C0IP_F32), ("f64_vcycle", P.C0IP_F64)):
+        p7 = P.Problem(2, args.N, args.k, omega=0.7, vcycle_dtype=dt)
+        x = torch.zeros_like(b)
+        info = p7.solve(b, x, max_iters=100, raise_on_nonconv=False)
+        om7[name] = {"converged": info["converged"], "iterations": info["iterations"],
+                     "status": {0: "OK", -4: "NOT_CONVERGED", -5: "ENAN"}.get(info.get("status", 0), "?"),
+                     "rel_res_est": info["rel_res_est"]}
+        p7.close()
+    out["avs_omega_0p7"] = om7
+    # --- 2D Q2 16^2 (1,089 DoFs): launch-latency bound; microseconds
+    from paper_2412_05082_amd.inputs import seeded_vector
+    k1, N1 = 2, 16
+    b1 = torch.from_numpy(seeded_vector(2, k1, N1, 0)).to(dev)
+    x1 = torch.from_numpy(seeded_vector(2, k1, N1, 1)).to(dev)
+    y1 = torch.empty_like(x1)
+    p1 = P.Problem(2, N1, k1, omega=0.25, vcycle_dtype=P.C0IP_F32)
+    us_mv = 1e3 * time_kernel(lambda _: p1.apply_A(x1, y1), [None], 200, torch)
+    us_sm = 1e3 * time_kernel(lambda _: p1.smoother_step(b1, x1, y1), [None], 200, torch)
+    xs = torch.zeros_like(b1)
+    sec, info = timed_solve(lambda: p1.solve(b1, xs), torch, reps=5)
+    out["c1_2d_q2_16"] = {"dofs": b1.numel(), "matvec_us": us_mv, "smoother_step_us": us_sm,
+                          "solve_ms": 1e3 * sec, "iterations": info["iterations"],
+                          "rel_res_true": info["rel_res_true"]}
+    p1.close()
     return out
 
 
@@ -243,6 +382,43 @@ def bench_sweep(args, torch, P):
         del xs, ref, b
         torch.cuda.empty_cache()
     return out
+
+
+# 3D mixed-precision workload: Q2, Q3 at 16^3..256^3 cells and Q4 at 16^3..128^3
+SWEEP3D = [(2, [16, 32, 64, 128, 256]), (3, [16, 32, 64, 128, 256]), (4, [16, 32, 64, 128])]
+
+
+def bench_3d_sweep(args, torch, P):
+    """3D MG-FGMRES with the coloured multiplicative smoother (16 colours,
+    omega 0.7, one pre- and post-step) to 1e-8: float32 V-cycle (mixed) vs
+    float64 V-cycle (double), DoFs solved per second and the speed-up, for
+    Q2..Q4 at the mesh sizes of the paper's mixed-precision study.  MVS
+    converges in a few iterations, so FGMRES restarts after 10 (keeps the
+    Krylov basis of the 454 M-DoF Q3 256^3 run at 40 GB)."""
+    from paper_2412_05082_amd.inputs import seeded_vector
+    dev = torch.device("cuda:0")
+    runs = []
+    for k, Ns in SWEEP3D:
+        for N in Ns:
+            b = torch.from_numpy(seeded_vector(3, k, N, 0)).to(dev)
+            row = {"degree": k, "cells": N, "dofs": b.numel()}
+            for name, dt in (("double", P.C0IP_F64), ("mixed", P.C0IP_F32)):
+                pb = P.Problem(3, N, k, omega=0.7, smoother=1, vcycle_dtype=dt)
+                x = torch.zeros_like(b)
+                sec, info = timed_solve(lambda: pb.solve(b, x, restart=10), torch, reps=1)
+                row[name] = {"seconds": sec, "iterations": info["iterations"], "frac_iters": info["frac_iters"],
+                             "dofs_per_s": b.numel() / sec, "rel_res_true": info["rel_res_true"]}
+                pb.close()
+                del x
+                torch.cuda.empty_cache()
+            row["speedup_mixed"] = row["double"]["seconds"] / row["mixed"]["seconds"]
+            runs.append(row)
+            print(f"3d sweep Q{k} {N}^3: double {row['double']['seconds']:.3f}s mixed {row['mixed']['seconds']:.3f}s",
+                  file=sys.stderr, flush=True)
+            del b
+            torch.cuda.empty_cache()
+    return {"workload": "3D C0IP biharmonic, MVS (16 colours, omega 0.7, 1+1 steps), FGMRES(10) to 1e-8, "
+                        "float32 vs float64 V-cycle", "runs": runs}
 
 
 def c5_problems():
@@ -329,14 +505,15 @@ def main():
 
     # --- per-kernel rates, cold HBM (rotating sets > 1 GB in total)
     nsets = max(4, int(1.2e9 // (3 * 8 * n)) + 1)
-    sets64 = [(torch.from_numpy(x_np).to(dev), torch.empty(n, dtype=torch.float64, device=dev), b)
+    # every set has its own x, y and b, so that no input of a timed launch is still in the last-level cache
+    sets64 = [(torch.from_numpy(x_np).to(dev), torch.empty(n, dtype=torch.float64, device=dev), b.clone())
               for _ in range(nsets)]
     ms_mv = time_kernel(lambda s: pmix.apply_A(s[0], s[1]), sets64, args.reps, torch)
     ms_sm0 = time_kernel(lambda s: pmix.smoother_step(s[2], None, s[1]), sets64, args.reps, torch)
     ms_smx = time_kernel(lambda s: pmix.smoother_step(s[2], s[0], s[1]), sets64, args.reps, torch)
     del sets64
     b32 = b.float()
-    sets32 = [(torch.from_numpy(x_np).float().to(dev), torch.zeros(n, dtype=torch.float32, device=dev), b32)
+    sets32 = [(torch.from_numpy(x_np).float().to(dev), torch.zeros(n, dtype=torch.float32, device=dev), b32.clone())
               for _ in range(nsets)]
     ms_mv32 = time_kernel(lambda s: pmix.apply_A(s[0], s[1]), sets32, args.reps, torch)
     ms_smx32 = time_kernel(lambda s: pmix.smoother_step(s[2], s[0], s[1]), sets32, args.reps, torch)
@@ -400,11 +577,13 @@ def main():
         },
         "kernels": {
             "matvec_f64": {"ms": ms_mv, "dofs_per_s": n / (ms_mv * 1e-3),
-                           "alg_GBs": 16.0 * n / (ms_mv * 1e-3) / 1e9},
+                           "alg_GBs": 16.0 * n / (ms_mv * 1e-3) / 1e9,
+                           "frac_hbm": 16.0 * n / (ms_mv * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "smoother_x0_f64": {"ms": ms_sm0, "dofs_per_s": n / (ms_sm0 * 1e-3),
                                 "alg_GBs": 16.0 * n / (ms_sm0 * 1e-3) / 1e9},
             "smoother_f64": {"ms": ms_smx, "dofs_per_s": n / (ms_smx * 1e-3),
-                             "alg_GBs": 24.0 * n / (ms_smx * 1e-3) / 1e9},
+                             "alg_GBs": 24.0 * n / (ms_smx * 1e-3) / 1e9,
+                             "frac_hbm": 24.0 * n / (ms_smx * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "matvec_f32": {"ms": ms_mv32, "dofs_per_s": n / (ms_mv32 * 1e-3),
                            "alg_GBs": 8.0 * n / (ms_mv32 * 1e-3) / 1e9},
             "smoother_f32": {"ms": ms_smx32, "dofs_per_s": n / (ms_smx32 * 1e-3),
@@ -420,6 +599,8 @@ def main():
                                f"S(x,b) (residual in LDS + patch solves), 12 B/DoF x {n} DoFs per launch; "
                                f"traffic = HBM bytes per launch from FETCH_SIZE/WRITE_SIZE"},
     }
+    if not args.no_extra:
+        out.update(bench_extra(args, torch, P, b, x_np))
     if not args.no_batch:
         out["config_batched"] = bench_batch(torch, P)
     if not args.no_sweep:
@@ -428,6 +609,8 @@ def main():
         del pmix, p64
         torch.cuda.empty_cache()
         out["config_3d_q3_128"] = bench_3d(args, torch, P)
+    if not args.no_3d_sweep:
+        out["config_3d_mixed_sweep"] = bench_3d_sweep(args, torch, P)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(k, args.cpu_N, args.omega)
     print(json.dumps(out), flush=True)

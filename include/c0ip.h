@@ -84,15 +84,23 @@ typedef struct {
  *   levels 0..m-1.  Ignored in 3D and for degree > 4.
  * smoother: 0 = additive vertex-patch Schwarz (AVS); 1 = coloured
  *   multiplicative vertex-patch Schwarz (MVS, Sec. 3 and Fig. 2): the
- *   vertices are split into 8 colours (2^d vertex-parity classes, each
- *   split red-black), patches of one colour share no node and no entry of
- *   A couples them; a step visits the colours in order c = 0..7 and for
+ *   vertices are split into colours (2^d vertex-parity classes, each split
+ *   red-black), patches of one colour share no node and no entry of A
+ *   couples them; a step visits the colours in order c = 0, 1, ... and for
  *   each forms the residual of the current iterate and adds omega times the
- *   local solves of that colour's patches (the paper uses omega = 1 in 2D).
- *   Colour of vertex v: sum_m (v_m mod 2) 2^m + 2^d ((sum_m floor(v_m / 2))
- *   mod 2).  MVS needs scatter_mode 0 (C0IP_EINVAL otherwise) and is built
- *   for 2D meshes (C0IP_EUNSUPPORTED in 3D and for batched solves).  Other
- *   values: C0IP_EINVAL. */
+ *   local solves of that colour's patches (the paper uses omega = 1 in 2D
+ *   and 0.7 in 3D).  2^(d+1) colours: 8 in 2D, 16 in 3D.  Colour of vertex
+ *   v: sum_m (v_m mod 2) 2^m + 2^d ((sum_m floor(v_m / 2)) mod 2).  MVS
+ *   needs scatter_mode 0 (C0IP_EINVAL otherwise); batched solves use the
+ *   additive smoother only (C0IP_EUNSUPPORTED).  Other values: C0IP_EINVAL.
+ * local_solver: 0 = the separable local matrix A~_v of eq. localsolverbila
+ *   inverted by fast diagonalisation (eq. inverse); 1 = the exact local
+ *   matrix A_v = R_v A R_v^T (mixed second derivatives kept; the comparison
+ *   of the paper's Tables 1 and 2), inverted densely at set-up (one inverse
+ *   per patch boundary type, float64 Cholesky, rounded for float32) and
+ *   applied as a dense product.  1 is built for 2D meshes with scatter_mode
+ *   0 (C0IP_EUNSUPPORTED otherwise, and for batched solves).  Other values:
+ *   C0IP_EINVAL. */
 typedef struct {
   double omega;
   int pre_steps, post_steps;
@@ -101,6 +109,7 @@ typedef struct {
   int scatter_mode;
   int tail_levels;
   int smoother;
+  int local_solver;
 } c0ip_mg_opts;
 
 /* Flexible GMRES options (Sec. 5.1: relative residual reduction 1e-8).
@@ -127,7 +136,8 @@ typedef struct {
 /* Create a problem: level hierarchy, 1D matrices, patch eigenbases, coarse
  * inverse, device tables and work space (Sec. 3-4).  opts may be NULL
  * (omega 1/4 in 2D and 0.1 in 3D, 1 pre- and 1 post-step, float32
- * V-cycle, exact coarse solve, tail_levels -1, additive smoother).  hip_stream is a hipStream_t or NULL.
+ * V-cycle, exact coarse solve, tail_levels -1, additive smoother with the
+ * separable local solver).  hip_stream is a hipStream_t or NULL.
  * On success *out owns all device memory it allocated. */
 c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, void* hip_stream,
                         c0ip_problem** out);
@@ -255,6 +265,11 @@ c0ip_status c0ip_host_matrices_1d(int degree, int n_cells, double gamma, double*
  * row-major entries (patch DoFs in lexicographic order, x fastest). */
 c0ip_status c0ip_host_patch_inverse(int dim, int degree, int n_cells, double gamma, const int* vertex,
                                     double* Ainv);
+/* The inverse of the exact local matrix A_v = R_v A R_v^T (the restriction
+ * of the operator of eq. bfc0ip to the patch's interior nodes, by its
+ * Kronecker form) used by local_solver 1: same layout as above. */
+c0ip_status c0ip_host_patch_inverse_exact(int dim, int degree, int n_cells, double gamma, const int* vertex,
+                                          double* Ainv);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,7 @@ class MeshDesc(C.Structure):
 class MgOpts(C.Structure):
     _fields_ = [("omega", C.c_double), ("pre_steps", C.c_int), ("post_steps", C.c_int),
                 ("vcycle_dtype", C.c_int), ("coarse_mode", C.c_int), ("scatter_mode", C.c_int),
-                ("tail_levels", C.c_int), ("smoother", C.c_int)]
+                ("tail_levels", C.c_int), ("smoother", C.c_int), ("local_solver", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -80,6 +80,8 @@ _SIGS = {
     "c0ip_host_matrices_1d": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "c0ip_host_patch_inverse": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_int),
                                           C.c_void_p]),
+    "c0ip_host_patch_inverse_exact": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_int),
+                                                C.c_void_p]),
 }
 
 
@@ -117,14 +119,16 @@ class Problem:
     """Owns a c0ip_problem handle (c0ip_create / c0ip_destroy)."""
 
     def __init__(self, dim, n_cells, degree, gamma=0.0, omega=None, pre_steps=1, post_steps=1,
-                 vcycle_dtype=C0IP_F32, coarse_mode=0, scatter_mode=0, tail_levels=-1, smoother=0, stream=None):
-        """smoother: 0 = additive (AVS), 1 = coloured multiplicative (MVS)."""
+                 vcycle_dtype=C0IP_F32, coarse_mode=0, scatter_mode=0, tail_levels=-1, smoother=0, local_solver=0,
+                 stream=None):
+        """smoother: 0 = additive (AVS), 1 = coloured multiplicative (MVS);
+        local_solver: 0 = separable (fast diagonalisation), 1 = exact (dense)."""
         lib = load_library()
         if omega is None:
             omega = 0.25 if dim == 2 else 0.1
         self.mesh = MeshDesc(dim, n_cells, degree, gamma)
         self.mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels,
-                         smoother)
+                         smoother, local_solver)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -209,8 +213,10 @@ class Problem:
         info = SolveInfo()
         st = load_library().c0ip_solve(self._h, C.byref(opts), self._vec(b, -1, C0IP_F64),
                                        self._vec(x, -1, C0IP_F64), C.byref(info))
-        if st == -4 and not raise_on_nonconv:
-            return info.as_dict()
+        if st in (-4, -5) and not raise_on_nonconv:  # NOT_CONVERGED / ENAN: info of the iterations done
+            d = info.as_dict()
+            d["status"] = st
+            return d
         _check(st)
         return info.as_dict()
 
@@ -230,13 +236,14 @@ class Batch:
     """Owns a c0ip_batch: problems = [(n_cells, degree), ...] (2D), n_rhs per problem."""
 
     def __init__(self, problems, n_rhs, gamma=0.0, omega=0.25, pre_steps=1, post_steps=1, vcycle_dtype=C0IP_F32,
-                 coarse_mode=0, tail_levels=-1, scatter_mode=0, smoother=0, stream=None):
+                 coarse_mode=0, tail_levels=-1, scatter_mode=0, smoother=0, local_solver=0, stream=None):
         lib = load_library()
         self.problems = list(problems)
         self.n_rhs = list(n_rhs)
         meshes = (MeshDesc * len(self.problems))(*[MeshDesc(2, N, k, gamma) for N, k in self.problems])
         rhs = (C.c_int * len(self.n_rhs))(*self.n_rhs)
-        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels, smoother)
+        mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels, smoother,
+                    local_solver)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -297,4 +304,13 @@ def host_patch_inverse(dim, degree, n_cells, vertex, gamma=0.0):
     out = np.zeros((n, n))
     v = (C.c_int * dim)(*vertex)
     _check(load_library().c0ip_host_patch_inverse(dim, degree, n_cells, gamma, v, out.ctypes.data))
+    return out
+
+
+def host_patch_inverse_exact(dim, degree, n_cells, vertex, gamma=0.0):
+    """Library's dense inverse of one exact patch matrix A_v = R_v A R_v^T."""
+    n = (2 * degree - 1) ** dim
+    out = np.zeros((n, n))
+    v = (C.c_int * dim)(*vertex)
+    _check(load_library().c0ip_host_patch_inverse_exact(dim, degree, n_cells, gamma, v, out.ctypes.data))
     return out

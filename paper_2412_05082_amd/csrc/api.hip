@@ -14,7 +14,9 @@
 #include "../../include/c0ip.h"
 #include "internal.h"
 #include "kernels.h"
+#include "exact.h"
 #include "krylov_cg.h"
+#include "mvs3d.h"
 #include "setup.h"
 
 namespace {
@@ -71,6 +73,7 @@ struct LevelWork {
   DevBuf<T> tabref;             // the table scaled to h = 1 (default penalty only)
   DevBuf<T> x, b, r, scratch;   // V-cycle vectors and transfer scratch
   DevBuf<T> t;                  // 2D: second iterate buffer (smoothing steps are out of place)
+  DevBuf<T> Aex;                // exact local solver: one dense patch inverse per boundary type
   c0ip::LevelCoef<T> coef;
   c0ip::LevelEig<T> eig;
   int avs_variant = 0;  // tile variant of the fused smoother (set by c0ip_autotune)
@@ -83,6 +86,7 @@ struct Level {
   c0ip::Level1D lv;
   c0ip::RowClasses rc;
   std::vector<double> tab, Q, lam;  // host copies (float64)
+  std::vector<double> Aex;          // exact local inverses [4 * 4][NN * NN] (local_solver 1)
   LevelWork<double> w64;
   LevelWork<float> w32;
 };
@@ -106,7 +110,34 @@ struct c0ip_problem {
   DevBuf<double> cg_p, cg_q, cg_z64, cg_sc, cg_partial;
   DevBuf<float> cg_z32;
   double* hpin = nullptr;  // pinned host staging for the per-step reductions
+  // The V-cycle of the Krylov solves as a captured graph, per precision
+  // ([0] float64, [1] float32): input u (float64; the float32 graph starts
+  // with the cast), output zfix.  Captured on first use and again when the
+  // buffers or a tile variant changed.
+  struct VGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* in = nullptr;
+    const void* out = nullptr;
+    void release() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+    }
+  } vgraph[2];
+  DevBuf<double> zfix64;
+  DevBuf<float> zfix32;
+  hipStream_t cap_stream = nullptr;  // capture only (the handle's stream may be the null stream)
+  void invalidate_graphs() {
+    vgraph[0].release();
+    vgraph[1].release();
+  }
+  template <typename T>
+  void vcycle_graph(const double* u, T* z);
   ~c0ip_problem() {
+    invalidate_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hpin) (void)hipHostFree(hpin);
   }
 
@@ -121,6 +152,11 @@ struct c0ip_problem {
   void smooth_from(int l, const T* b, T* from, T* x, int steps);
   template <typename T>
   void smooth_mvs(int l, const T* b, T* x, T* r, int steps, bool x_is_zero);
+  // the 2D additive step fused with its residual (separable local solver, owner computes)
+  bool fused2d() const { return dim == 2 && mg.scatter_mode == 0 && mg.smoother == 0 && mg.local_solver == 0; }
+  // x_out = x_in + omega * sum_v R_v^T (local inverse) R_v r (owner computes; x_in may be null or x_out)
+  template <typename T>
+  void patch_step(int l, const T* r, const T* x_in, T* x_out, T om);
   template <typename T>
   void mg_level(int l, const T* b, T* x);
   template <typename T>
@@ -174,6 +210,7 @@ void c0ip_problem::prepare(int l) {
   }
   w.eig.Q = w.Q.p;
   w.eig.lam = w.lam.p;
+  if (!L_.Aex.empty()) w.Aex.upload(cast_vec<T>(L_.Aex));
   w.x.alloc(L_.ntot);
   w.b.alloc(L_.ntot);
   w.r.alloc(L_.ntot);
@@ -216,7 +253,7 @@ void c0ip_problem::smooth(int l, const T* b, T* x, int steps, bool x_is_zero) {
   }
   int s0 = 0;
   if (x_is_zero) {
-    check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, b, nullptr, x, om, stream), "smoother");
+    patch_step<T>(l, b, nullptr, x, om);
     s0 = 1;
   }
   smooth_from(l, b, x, x, steps - s0);
@@ -234,7 +271,7 @@ void c0ip_problem::smooth_from(int l, const T* b, T* from, T* x, int steps) {
     smooth<T>(l, b, x, steps, false);
     return;
   }
-  if (dim == 2) {
+  if (fused2d()) {
     T* cur = from;
     T* oth = (from == x) ? w.r.p : x;
     for (int s = 0; s < steps; ++s) {
@@ -249,12 +286,21 @@ void c0ip_problem::smooth_from(int l, const T* b, T* from, T* x, int steps) {
   if (from != x) check(hipMemcpyAsync(x, from, sizeof(T) * lv[l]->ntot, hipMemcpyDeviceToDevice, stream), "copy");
   for (int s = 0; s < steps; ++s) {
     check(c0ip::launch_apply<T, T>(dim, k, Nl, w.coef, x, b, w.r.p, stream), "residual");
-    check(c0ip::launch_patch_smooth<T>(dim, k, Nl, w.eig, w.r.p, x, x, om, stream), "smoother");
+    patch_step<T>(l, w.r.p, x, x, om);
   }
 }
 
+template <typename T>
+void c0ip_problem::patch_step(int l, const T* r, const T* x_in, T* x_out, T om) {
+  LevelWork<T>& w = work<T>(l);
+  if (mg.local_solver == 1)
+    check(c0ip::launch_patch2d_exact<T>(k, lv[l]->N, w.Aex.p, r, x_in, x_out, om, stream), "exact local solves");
+  else
+    check(c0ip::launch_patch_smooth<T>(dim, k, lv[l]->N, w.eig, r, x_in, x_out, om, stream), "smoother");
+}
+
 // `steps` steps of the coloured multiplicative smoother on level l, in
-// place on x: per colour c = 0..7, r = b - A x (r = b for the first colour
+// place on x: per colour c = 0..2^(d+1)-1, r = b - A x (r = b for the first colour
 // of a step from x = 0), then x += omega * (local solves of colour c).
 template <typename T>
 void c0ip_problem::smooth_mvs(int l, const T* b, T* x, T* r, int steps, bool x_is_zero) {
@@ -271,7 +317,12 @@ void c0ip_problem::smooth_mvs(int l, const T* b, T* x, T* r, int steps, bool x_i
       } else {
         check(c0ip::launch_apply<T, T>(dim, k, Nl, w.coef, x, b, r, stream), "residual");
       }
-      check(c0ip::launch_mvs2d_colour<T>(k, Nl, c, w.eig, rc, x, om, stream), "multiplicative smoother colour");
+      if (dim == 2 && mg.local_solver == 1)
+        check(c0ip::launch_mvs2d_colour_exact<T>(k, Nl, c, w.Aex.p, rc, x, om, stream), "multiplicative colour");
+      else if (dim == 2)
+        check(c0ip::launch_mvs2d_colour<T>(k, Nl, c, w.eig, rc, x, om, stream), "multiplicative smoother colour");
+      else
+        check(c0ip::launch_mvs3d_colour<T>(k, Nl, c, w.eig, rc, x, om, stream), "multiplicative smoother colour");
     }
 }
 
@@ -283,7 +334,7 @@ int c0ip_problem::tail_level() {
   int& t = tailLT[sizeof(T) == 4 ? 1 : 0];
   if (t != -2) return t;
   t = -1;
-  if (dim != 2 || k > 4 || mg.tail_levels == 0 || mg.scatter_mode != 0 || mg.smoother != 0) return t;
+  if (dim != 2 || k > 4 || mg.tail_levels == 0 || !fused2d()) return t;
   const int lim = c0ip::tail_lds_limit();
   int cap = std::min(L, c0ip::kTailMaxLevels - 1);
   if (mg.tail_levels > 0) cap = std::min(cap, mg.tail_levels - 1);
@@ -389,14 +440,13 @@ void c0ip_problem::mg_level(int l, const T* b, T* x) {
     if (mg.coarse_mode == 0) {
       check(c0ip::launch_coarse<T>(dim, k, A0inv.p, b, x, stream), "coarse solve");
     } else {
-      LevelWork<T>& w = work<T>(0);
-      check(c0ip::launch_patch_smooth<T>(dim, k, lv[0]->N, w.eig, b, nullptr, x, T(1), stream), "coarse smooth");
+      patch_step<T>(0, b, nullptr, x, T(1));
     }
     return;
   }
   LevelWork<T>& w = work<T>(l);
   LevelWork<T>& wc = work<T>(l - 1);
-  if (dim == 2 && mg.scatter_mode == 0 && mg.smoother == 0) {
+  if (fused2d()) {
     mg_level2d<T>(l, b, x);
     return;
   }
@@ -408,6 +458,47 @@ void c0ip_problem::mg_level(int l, const T* b, T* x) {
     check(c0ip::launch_prolong_add<T>(dim, k, lv[l - 1]->N, w.ptab.p, wc.x.p, x, w.scratch.p, stream), "prolong");
     smooth<T>(l, b, x, mg.post_steps, false);
   }
+}
+
+// z = MG_L(0, u) in precision T (u float64; the float32 form casts it into
+// the finest level's b first), as one replay of a captured graph.  Every
+// launch of the V-cycle goes to the handle's stream and allocates nothing
+// once the levels are prepared, so the captured sequence is the eager one.
+template <typename T>
+void c0ip_problem::vcycle_graph(const double* u, T* z) {
+  VGraph& g = vgraph[sizeof(T) == 4 ? 1 : 0];
+  if (!g.exec || g.in != u || g.out != z) {
+    g.release();
+    for (int l = 0; l <= L; ++l) prepare<T>(l);
+    (void)tail_level<T>();  // sets the tail kernel's LDS attribute outside the capture
+    if (!cap_stream) check(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking), "capture stream");
+    // record on the capture stream; the graph is launched on the handle's stream
+    const hipStream_t user = stream;
+    stream = cap_stream;
+    check(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      if constexpr (sizeof(T) == 4) {
+        LevelWork<float>& wf = work<float>(L);
+        check(c0ip::launch_cast<double, float>(ntot(L), u, wf.b.p, stream), "cast");
+        mg_level<float>(L, wf.b.p, (float*)z);
+      } else {
+        mg_level<double>(L, u, (double*)z);
+      }
+    } catch (...) {
+      hipGraph_t dead = nullptr;
+      (void)hipStreamEndCapture(stream, &dead);
+      if (dead) (void)hipGraphDestroy(dead);
+      stream = user;
+      throw;
+    }
+    const hipError_t ec = hipStreamEndCapture(stream, &g.graph);
+    stream = user;
+    check(ec, "end capture");
+    check(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0), "graph instantiate");
+    g.in = u;
+    g.out = z;
+  }
+  check(hipGraphLaunch(g.exec, stream), "graph launch");
 }
 
 namespace {
@@ -539,14 +630,14 @@ void smoother_step_on(c0ip_problem* p, int l, const T* b, const T* x_in, T* x_ou
     }
     p->check(c0ip::launch_patch2d_atomic<T>(p->k, Nl, w.eig, x_in ? r : b, x_out, om, p->stream), "atomic smoother");
   } else if (!x_in) {
-    p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, b, nullptr, x_out, om, p->stream), "smoother");
-  } else if (p->dim == 2) {
+    p->patch_step<T>(l, b, nullptr, x_out, om);
+  } else if (p->fused2d()) {
     p->check(c0ip::launch_avs2d<T>(p->k, Nl, w.coef, w.eig, x_in, b, x_out, om, p->stream, 1, 0, nullptr,
                                    w.avs_variant),
              "fused smoother");
   } else {
     p->check(c0ip::launch_apply<T, T>(p->dim, p->k, Nl, w.coef, x_in, b, r, p->stream), "residual");
-    p->check(c0ip::launch_patch_smooth<T>(p->dim, p->k, Nl, w.eig, r, x_in, x_out, om, p->stream), "smoother");
+    p->patch_step<T>(l, r, x_in, x_out, om);
   }
 }
 
@@ -574,13 +665,15 @@ c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, vo
     mg.scatter_mode = 0;
     mg.tail_levels = -1;
     mg.smoother = 0;
+    mg.local_solver = 0;
   }
   if (!(mg.omega > 0) || !std::isfinite(mg.omega)) return fail(C0IP_EINVAL, "omega must be > 0");
   if (mg.smoother != 0 && mg.smoother != 1) return fail(C0IP_EINVAL, "smoother must be 0 or 1");
   if (mg.smoother == 1 && mg.scatter_mode != 0)
     return fail(C0IP_EINVAL, "the multiplicative smoother takes scatter_mode 0");
-  if (mg.smoother == 1 && mesh->dim != 2)
-    return fail(C0IP_EUNSUPPORTED, "the multiplicative smoother is built for 2D meshes only");
+  if (mg.local_solver != 0 && mg.local_solver != 1) return fail(C0IP_EINVAL, "local_solver must be 0 or 1");
+  if (mg.local_solver == 1 && (mesh->dim != 2 || mg.scatter_mode != 0))
+    return fail(C0IP_EUNSUPPORTED, "the exact local solver is built for 2D meshes with scatter_mode 0");
   if (mg.pre_steps < 0 || mg.post_steps < 0 || mg.pre_steps > 16 || mg.post_steps > 16)
     return fail(C0IP_EINVAL, "smoothing steps must be in [0,16]");
   if (mg.vcycle_dtype != C0IP_F64 && mg.vcycle_dtype != C0IP_F32) return fail(C0IP_EINVAL, "bad vcycle_dtype");
@@ -646,6 +739,22 @@ c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, vo
           std::copy(pe.Q[t].begin(), pe.Q[t].end(), lv->Q.begin() + (size_t)t * n * n);
           std::copy(pe.lam[t].begin(), pe.lam[t].end(), lv->lam.begin() + (size_t)t * n);
         }
+      if (p->mg.local_solver == 1) {
+        // one dense inverse of the exact local matrix per boundary type (tx, ty) present on the level
+        const int NN = n * n, Nl = lv->N;
+        int rep[4] = {-1, -1, -1, -1};
+        for (int v = 1; v <= Nl - 1; ++v)
+          if (rep[c0ip::patch_variant(v, Nl)] < 0) rep[c0ip::patch_variant(v, Nl)] = v;
+        lv->Aex.assign((size_t)16 * NN * NN, 0.0);
+        for (int ty = 0; ty < 4; ++ty)
+          for (int tx = 0; tx < 4; ++tx) {
+            if (rep[tx] < 0 || rep[ty] < 0) continue;
+            const int vert[2] = {rep[tx], rep[ty]};
+            std::vector<double> inv;
+            if (!c0ip::patch_exact_inverse(lv->lv, 2, vert, inv, err)) return fail(C0IP_EINVAL, err);
+            std::copy(inv.begin(), inv.end(), lv->Aex.begin() + (size_t)(ty * 4 + tx) * NN * NN);
+          }
+      }
       p->lv.push_back(std::move(lv));
     }
     std::vector<double> Ainv;
@@ -773,7 +882,7 @@ c0ip_status c0ip_smoother_step_noalloc(c0ip_problem* p, int level, c0ip_dtype dt
                              "(or by an earlier float32 call of another entry point)");
   // the residual goes through the work space in 3D, with the atomic scatter
   // and with the multiplicative smoother (after its first colour, also from 0)
-  const bool needs_r = p->mg.smoother == 1 || (x_in && (p->dim == 3 || p->mg.scatter_mode == 1));
+  const bool needs_r = p->mg.smoother == 1 || (x_in && !p->fused2d());
   void* r = nullptr;
   if (needs_r) {
     if ((size_t)p->ntot(l) * esz > kNoAllocScratchBytes)
@@ -833,6 +942,7 @@ c0ip_status c0ip_autotune(c0ip_problem* p, int reps) {
           }
         }
         w.avs_variant = bestv;
+        p->invalidate_graphs();
       }
     };
     tune(double{});
@@ -852,6 +962,7 @@ c0ip_status c0ip_set_variant(c0ip_problem* p, int level, c0ip_dtype dtype, int v
   const int l = resolve_level(p, level);
   if (dtype == C0IP_F32) p->lv[l]->w32.avs_variant = variant;
   else p->lv[l]->w64.avs_variant = variant;
+  p->invalidate_graphs();
   return C0IP_OK;
 }
 
@@ -925,6 +1036,8 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   double t_vc = 0;
   c0ip_status result = C0IP_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr, ef = nullptr;
+  int its = 0;
+  double last_est = 0, bnorm_out = 0;
   try {
     const int nblk = std::max(c0ip::multidot_blocks(n), c0ip::arnoldi_blocks(n));
     const int nblk_a = c0ip::arnoldi_blocks(n);
@@ -939,9 +1052,11 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     if (!p->hpin) p->check(hipHostMalloc((void**)&p->hpin, sizeof(double) * (4 * 64 + 16)), "pinned alloc");
     if (f32) {
       p->Z32.alloc((size_t)m * n);
+      p->zfix32.alloc(n);
       for (int l = 0; l <= Lf; ++l) p->prepare<float>(l);
     } else {
       p->Z64.alloc((size_t)m * n);
+      p->zfix64.alloc(n);
     }
     p->check(hipEventCreate(&e0), "event");
     p->check(hipEventCreate(&e1), "event");
@@ -960,6 +1075,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, p->w.p, b, p->r64.p, s), "mask b");
     const double bnorm = std::sqrt(norm2(p->r64.p));
     if (!std::isfinite(bnorm)) throw c0ip_status(C0IP_ENAN);
+    bnorm_out = bnorm;
     if (opts->x0_is_zero) {
       p->check(c0ip::launch_fill(n, 0.0, x, s), "fill");
     } else {
@@ -967,7 +1083,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     }
     double beta = std::sqrt(norm2(p->r64.p));
     std::vector<double> hist{beta};
-    int its = 0;
+    last_est = beta;
     bool converged = bnorm == 0.0 || beta <= opts->rtol * bnorm;
     std::vector<double> H((size_t)(m + 1) * m), R, g, y(m);
     while (!converged && its < opts->max_iters) {
@@ -986,16 +1102,16 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
         bool zf32 = f32;
         if (f32) {
           float* Zj = p->Z32.p + (size_t)j * n;
-          LevelWork<float>& wf = p->work<float>(Lf);
-          p->check(c0ip::launch_cast<double, float>(n, p->u.p, wf.b.p, s), "cast");
-          p->mg_level<float>(Lf, wf.b.p, Zj);
+          p->vcycle_graph<float>(p->u.p, p->zfix32.p);
           p->check(hipEventRecord(e1, s), "event");
+          p->check(hipMemcpyAsync(Zj, p->zfix32.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s), "copy z");
           p->check(c0ip::launch_apply<float, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
           Zp = nullptr;
         } else {
           double* Zj = p->Z64.p + (size_t)j * n;
-          p->mg_level<double>(Lf, p->u.p, Zj);
+          p->vcycle_graph<double>(p->u.p, p->zfix64.p);
           p->check(hipEventRecord(e1, s), "event");
+          p->check(hipMemcpyAsync(Zj, p->zfix64.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy z");
           p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
           Zp = Zj;
         }
@@ -1041,6 +1157,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
         ++its;
         jdone = j + 1;
         hist.push_back(res);
+        last_est = res;
         if (res <= opts->rtol * bnorm || H[(size_t)(j + 1) * m + j] == 0.0 || its >= opts->max_iters) stop = true;
       }
       // y = R^{-1} g, x += Z y
@@ -1072,7 +1189,9 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     result = hip_fail(h);
   } catch (c0ip_status st) {
     (void)hipStreamSynchronize(s);
-    result = fail(st, "non-finite value in the Krylov iteration");
+    result = fail(st, "non-finite value in the Krylov iteration (iteration " + std::to_string(its + 1) + ")");
+    inf.iterations = its;
+    inf.rel_res_est = bnorm_out > 0 ? last_est / bnorm_out : 0.0;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -1146,13 +1265,8 @@ c0ip_status c0ip_solve_fcg(c0ip_problem* p, const c0ip_krylov_opts* opts, const 
       if (!std::isfinite(rr)) throw c0ip_status(C0IP_ENAN);
       const int first = its == 0;
       p->check(hipEventRecord(e0, s), "event");
-      if (f32) {
-        LevelWork<float>& wf = p->work<float>(Lf);
-        p->check(c0ip::launch_cast<double, float>(n, r, wf.b.p, s), "cast");
-        p->mg_level<float>(Lf, wf.b.p, p->cg_z32.p);
-      } else {
-        p->mg_level<double>(Lf, r, p->cg_z64.p);
-      }
+      if (f32) p->vcycle_graph<float>(r, p->cg_z32.p);
+      else p->vcycle_graph<double>(r, p->cg_z64.p);
       p->check(hipEventRecord(e1, s), "event");
       // beta = (z . q_old) / (p_old . q_old); p = z - beta p_old
       if (!first) {
@@ -1217,6 +1331,22 @@ c0ip_status c0ip_host_matrices_1d(int degree, int n_cells, double gamma, double*
       L[(size_t)i * n1 + j] = lv.L.get(i, j);
       B[(size_t)i * n1 + j] = lv.B.get(i, j);
     }
+  return C0IP_OK;
+}
+
+c0ip_status c0ip_host_patch_inverse_exact(int dim, int degree, int n_cells, double gamma, const int* vertex,
+                                          double* Ainv) {
+  g_err.clear();
+  if ((dim != 2 && dim != 3) || degree < 2 || degree > 7 || !is_pow2(n_cells) || !vertex || !Ainv)
+    return fail(C0IP_EINVAL, "bad argument");
+  for (int d = 0; d < dim; ++d)
+    if (vertex[d] < 1 || vertex[d] > n_cells - 1) return fail(C0IP_EINVAL, "vertex out of range");
+  const double gam = gamma > 0 ? gamma : (double)(degree * (degree + 1));
+  c0ip::Level1D lv = c0ip::build_level_1d(degree, n_cells, gam);
+  std::vector<double> inv;
+  std::string err;
+  if (!c0ip::patch_exact_inverse(lv, dim, vertex, inv, err)) return fail(C0IP_EINVAL, err);
+  std::copy(inv.begin(), inv.end(), Ainv);
   return C0IP_OK;
 }
 

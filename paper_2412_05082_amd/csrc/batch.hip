@@ -525,11 +525,14 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
     mg.scatter_mode = 0;
     mg.tail_levels = -1;
     mg.smoother = 0;
+    mg.local_solver = 0;
   }
   if (mg.scatter_mode != 0)
     return bfail(C0IP_EUNSUPPORTED, "batched solves use the owner-computes smoother (scatter_mode 0)");
   if (mg.smoother != 0)
     return bfail(C0IP_EUNSUPPORTED, "batched solves use the additive smoother (smoother 0)");
+  if (mg.local_solver != 0)
+    return bfail(C0IP_EUNSUPPORTED, "batched solves use the separable local solver (local_solver 0)");
   std::unique_ptr<c0ip_batch> bt(new c0ip_batch());
   bt->mg = mg;
   bt->user = (hipStream_t)hip_stream;

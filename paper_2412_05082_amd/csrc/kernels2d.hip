@@ -9,6 +9,7 @@
 // twice instead of racing on writes), and writes each owned DoF once.
 #include <algorithm>
 
+#include "exact.h"
 #include "kernels.h"
 #include "tiles.h"
 
@@ -176,6 +177,82 @@ hipError_t patch2d_k(int N, const LevelEig<T>& e, const T* r, const T* xin, T* x
   return hipGetLastError();
 }
 
+// Owner-computes smoother step with exact local solves: as patch2d_kernel,
+// but each patch correction is the dense product A_v^{-1} r_v (one inverse
+// per patch type, read through the cache; on interior tiles every patch has
+// the interior type, so the reads are wave-uniform across patches).
+template <typename T, int K, int TC>
+__global__ __launch_bounds__(kThreads) void patch2d_exact_kernel(const T* __restrict__ r, const T* __restrict__ xin,
+                                                                 T* __restrict__ xout, int N, int n1,
+                                                                 const T* __restrict__ Aex, T omega) {
+  constexpr int n = 2 * K - 1, NN = n * n, NP = TC + 1, S = (TC + 2) * K - 1;
+  __shared__ T sR[S * S];
+  __shared__ T sA[NP * NP * NN];
+  int tbx, tby;
+  xcd_tile(tbx, tby);
+  const int cx0 = tbx * TC, cy0 = tby * TC;
+  const int ox = (cx0 - 1) * K + 1, oy = (cy0 - 1) * K + 1;  // global node of region (0,0)
+  for (int e = threadIdx.x; e < S * S; e += kThreads) {
+    const int rr = e / S, cc = e - rr * S;
+    const int gy = oy + rr, gx = ox + cc;
+    sR[e] = (gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2) ? r[(size_t)gy * n1 + gx] : T(0);
+  }
+  __syncthreads();
+  // u[i] = sum_j A_v^{-1}[i][j] r_v[j] for every patch touching the tile
+  for (int it = threadIdx.x; it < NP * NP * NN; it += kThreads) {
+    const int p = it / NN, i = it - p * NN;
+    const int pyl = p / NP, pxl = p - pyl * NP;
+    const int vx = cx0 + pxl, vy = cy0 + pyl;
+    if (vx < 1 || vx > N - 1 || vy < 1 || vy > N - 1) continue;
+    const T* row = Aex + (size_t)(variant(vy, N) * 4 + variant(vx, N)) * NN * NN + (size_t)i * NN;
+    T s = 0;
+    for (int a = 0; a < n; ++a) {
+      const T* rr = sR + (pyl * K + a) * S + pxl * K;
+#pragma unroll
+      for (int c = 0; c < n; ++c) s += row[a * n + c] * rr[c];
+    }
+    sA[it] = s;
+  }
+  __syncthreads();
+  constexpr int OW = TC * K + 1;
+  const int gx0 = cx0 * K, gy0 = cy0 * K;
+  const int gx1 = (cx0 + TC >= N) ? n1 : (cx0 + TC) * K;
+  const int gy1 = (cy0 + TC >= N) ? n1 : (cy0 + TC) * K;
+  for (int e = threadIdx.x; e < OW * OW; e += kThreads) {
+    const int jj = e / OW, ii = e - jj * OW;
+    const int gx = gx0 + ii, gy = gy0 + jj;
+    if (gx >= gx1 || gy >= gy1) continue;
+    const size_t idx = (size_t)gy * n1 + gx;
+    if (gx == 0 || gx == n1 - 1 || gy == 0 || gy == n1 - 1) {
+      xout[idx] = T(0);
+      continue;
+    }
+    const int vxa = gx / K, vxb = (gx % K == 0) ? vxa : vxa + 1;
+    const int vya = gy / K, vyb = (gy % K == 0) ? vya : vya + 1;
+    T acc = 0;
+    for (int vy = vya; vy <= vyb; ++vy) {
+      if (vy < 1 || vy > N - 1) continue;
+      for (int vx = vxa; vx <= vxb; ++vx) {
+        if (vx < 1 || vx > N - 1) continue;
+        const int p = (vy - cy0) * NP + (vx - cx0);
+        const int c = gx - ((vx - 1) * K + 1), a = gy - ((vy - 1) * K + 1);
+        acc += sA[p * NN + a * n + c];
+      }
+    }
+    xout[idx] = (xin ? xin[idx] : T(0)) + omega * acc;
+  }
+}
+
+template <int K> struct ExactTile2D { static constexpr int TC = K <= 3 ? 8 : 4; };
+
+template <typename T, int K>
+hipError_t patch2d_exact_k(int N, const T* Aex, const T* r, const T* xin, T* xout, T omega, hipStream_t s) {
+  constexpr int TC = ExactTile2D<K>::TC;
+  const int nt = (N + TC - 1) / TC;
+  patch2d_exact_kernel<T, K, TC><<<dim3(nt, nt), kThreads, 0, s>>>(r, xin, xout, N, K * N + 1, Aex, omega);
+  return hipGetLastError();
+}
+
 // Atomic-scatter form of the smoother step (the comparison variant): a
 // workgroup solves TC x TC patches, each exactly once (no redundant border
 // patches), and adds omega times every patch correction into x_out with
@@ -328,11 +405,11 @@ __device__ __forceinline__ void colour_vertex(const ColourRows& cr, int px, int 
 
 template <int K> struct ColourPatches { static constexpr int NPW = kThreads / (2 * K - 1); };
 
-template <typename T, int K>
+template <typename T, int K, bool EXACT>
 __global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restrict__ r, T* __restrict__ x, int N,
                                                                 int n1, ColourRows cr, int px, int py,
                                                                 const T* __restrict__ Qg, const T* __restrict__ lamg,
-                                                                T omega) {
+                                                                const T* __restrict__ Aex, T omega) {
   constexpr int n = 2 * K - 1, NN = n * n, NPW = ColourPatches<K>::NPW;
   __shared__ T sA[NPW * NN];
   __shared__ T sB[NPW * NN];
@@ -347,6 +424,29 @@ __global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restr
     int vx, vy;
     colour_vertex(cr, px, py, q0 + p, vx, vy);
     sB[e] = r[(size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c];
+  }
+  if constexpr (EXACT) {
+    // exact local solves: u = A_v^{-1} r_v, one dense row per thread and patch
+    __syncthreads();
+    for (int it = threadIdx.x; it < np * NN; it += kThreads) {
+      const int p = it / NN, i = it - p * NN;
+      int vx, vy;
+      colour_vertex(cr, px, py, q0 + p, vx, vy);
+      const T* row = Aex + (size_t)(variant(vy, N) * 4 + variant(vx, N)) * NN * NN + (size_t)i * NN;
+      const T* rv = sB + p * NN;
+      T s = 0;
+      for (int j = 0; j < NN; ++j) s += row[j] * rv[j];
+      sA[it] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * NN; e += kThreads) {
+      const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
+      int vx, vy;
+      colour_vertex(cr, px, py, q0 + p, vx, vy);
+      const size_t g = (size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c;
+      x[g] = x[g] + omega * sA[e];
+    }
+    return;
   }
   for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
   for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
@@ -428,8 +528,19 @@ hipError_t mvs2d_colour_k(int N, int colour, const LevelEig<T>& e, const T* r, T
   const ColourRows cr = colour_rows(N, colour);
   if (cr.total <= 0) return hipSuccess;
   const int nblk = (cr.total + NPW - 1) / NPW;
-  mvs2d_colour_kernel<T, K><<<nblk, kThreads, 0, s>>>(r, x, N, K * N + 1, cr, colour & 1, (colour >> 1) & 1, e.Q,
-                                                     e.lam, omega);
+  mvs2d_colour_kernel<T, K, false><<<nblk, kThreads, 0, s>>>(r, x, N, K * N + 1, cr, colour & 1, (colour >> 1) & 1,
+                                                            e.Q, e.lam, nullptr, omega);
+  return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t mvs2d_colour_exact_k(int N, int colour, const T* Aex, const T* r, T* x, T omega, hipStream_t s) {
+  constexpr int NPW = ColourPatches<K>::NPW;
+  const ColourRows cr = colour_rows(N, colour);
+  if (cr.total <= 0) return hipSuccess;
+  const int nblk = (cr.total + NPW - 1) / NPW;
+  mvs2d_colour_kernel<T, K, true><<<nblk, kThreads, 0, s>>>(r, x, N, K * N + 1, cr, colour & 1, (colour >> 1) & 1,
+                                                           nullptr, nullptr, Aex, omega);
   return hipGetLastError();
 }
 
@@ -615,6 +726,22 @@ hipError_t launch_mvs2d_colour(int k, int N, int colour, const LevelEig<T>& e, c
 }
 
 template <typename T>
+hipError_t launch_patch2d_exact(int k, int N, const T* Aex, const T* r, const T* xin, T* xout, T omega,
+                                hipStream_t s) {
+#define CALL(K) patch2d_exact_k<T, K>(N, Aex, r, xin, xout, omega, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template <typename T>
+hipError_t launch_mvs2d_colour_exact(int k, int N, int colour, const T* Aex, const T* r, T* x, T omega,
+                                     hipStream_t s) {
+#define CALL(K) mvs2d_colour_exact_k<T, K>(N, colour, Aex, r, x, omega, s)
+  C0IP_DISPATCH_K(k, CALL)
+#undef CALL
+}
+
+template <typename T>
 hipError_t launch_restrict2d(int k, int Nc, const T* table, const T* rf, T* bc, hipStream_t s, int nsys,
                              int64_t zf, int64_t zc, const int* active) {
 #define CALL(K) restrict2d_k<T, K>(Nc, table, rf, bc, s, nsys, zf, zc, active)
@@ -646,6 +773,14 @@ template hipError_t launch_mvs2d_colour<double>(int, int, int, const LevelEig<do
                                                 double, hipStream_t);
 template hipError_t launch_mvs2d_colour<float>(int, int, int, const LevelEig<float>&, const float*, float*, float,
                                                hipStream_t);
+template hipError_t launch_patch2d_exact<double>(int, int, const double*, const double*, const double*, double*,
+                                                 double, hipStream_t);
+template hipError_t launch_patch2d_exact<float>(int, int, const float*, const float*, const float*, float*, float,
+                                                hipStream_t);
+template hipError_t launch_mvs2d_colour_exact<double>(int, int, int, const double*, const double*, double*, double,
+                                                      hipStream_t);
+template hipError_t launch_mvs2d_colour_exact<float>(int, int, int, const float*, const float*, float*, float,
+                                                     hipStream_t);
 template hipError_t launch_patch2d<double>(int, int, const LevelEig<double>&, const double*, const double*,
                                            double*, double, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_patch2d<float>(int, int, const LevelEig<float>&, const float*, const float*, float*,

@@ -364,31 +364,34 @@ std::vector<double> prolongation_table(int k) {
   return T;
 }
 
-bool coarse_inverse(const Level1D& lv0, int dim, std::vector<double>& Ainv, std::string& err) {
-  const int k = lv0.k, n = 2 * k - 1;
-  int n0 = 1;
-  for (int d = 0; d < dim; ++d) n0 *= n;
-  auto M = [&](int i, int j) { return lv0.M.get(i + 1, j + 1); };
-  auto L = [&](int i, int j) { return lv0.L.get(i + 1, j + 1); };
-  auto B = [&](int i, int j) { return lv0.B.get(i + 1, j + 1); };
+bool patch_exact_inverse(const Level1D& lv, int dim, const int* v, std::vector<double>& Ainv, std::string& err) {
+  const int k = lv.k, n = 2 * k - 1;
+  int n0 = 1, i0[3] = {1, 1, 1};
+  for (int d = 0; d < dim; ++d) {
+    n0 *= n;
+    i0[d] = (v[d] - 1) * k + 1;  // first interior node of the patch along axis d
+  }
+  auto M = [&](int d, int i, int j) { return lv.M.get(i0[d] + i, i0[d] + j); };
+  auto L = [&](int d, int i, int j) { return lv.L.get(i0[d] + i, i0[d] + j); };
+  auto B = [&](int d, int i, int j) { return lv.B.get(i0[d] + i, i0[d] + j); };
   std::vector<double> A((size_t)n0 * n0);
   for (int r = 0; r < n0; ++r)
     for (int c = 0; c < n0; ++c) {
       int ri[3] = {r % n, (r / n) % n, r / (n * n)}, ci[3] = {c % n, (c / n) % n, c / (n * n)};
-      double v;
+      double val;
       if (dim == 2) {
-        v = B(ri[0], ci[0]) * M(ri[1], ci[1]) + 2 * L(ri[0], ci[0]) * L(ri[1], ci[1]) +
-            M(ri[0], ci[0]) * B(ri[1], ci[1]);
+        val = B(0, ri[0], ci[0]) * M(1, ri[1], ci[1]) + 2 * L(0, ri[0], ci[0]) * L(1, ri[1], ci[1]) +
+              M(0, ri[0], ci[0]) * B(1, ri[1], ci[1]);
       } else {
-        double m0 = M(ri[0], ci[0]), m1 = M(ri[1], ci[1]), m2 = M(ri[2], ci[2]);
-        double l0 = L(ri[0], ci[0]), l1 = L(ri[1], ci[1]), l2 = L(ri[2], ci[2]);
-        double b0 = B(ri[0], ci[0]), b1 = B(ri[1], ci[1]), b2 = B(ri[2], ci[2]);
-        v = b0 * m1 * m2 + m0 * b1 * m2 + m0 * m1 * b2 + 2 * (l0 * l1 * m2 + m0 * l1 * l2 + l0 * m1 * l2);
+        double m0 = M(0, ri[0], ci[0]), m1 = M(1, ri[1], ci[1]), m2 = M(2, ri[2], ci[2]);
+        double l0 = L(0, ri[0], ci[0]), l1 = L(1, ri[1], ci[1]), l2 = L(2, ri[2], ci[2]);
+        double b0 = B(0, ri[0], ci[0]), b1 = B(1, ri[1], ci[1]), b2 = B(2, ri[2], ci[2]);
+        val = b0 * m1 * m2 + m0 * b1 * m2 + m0 * m1 * b2 + 2 * (l0 * l1 * m2 + m0 * l1 * l2 + l0 * m1 * l2);
       }
-      A[(size_t)r * n0 + c] = v;
+      A[(size_t)r * n0 + c] = val;
     }
   std::vector<double> C = A;
-  if (!cholesky(n0, C)) { err = "coarse operator not positive definite"; return false; }
+  if (!cholesky(n0, C)) { err = "local operator not positive definite"; return false; }
   // inverse from the Cholesky factor: solve C C^T X = I column by column
   Ainv.assign((size_t)n0 * n0, 0.0);
   std::vector<double> y(n0);
@@ -403,6 +406,15 @@ bool coarse_inverse(const Level1D& lv0, int dim, std::vector<double>& Ainv, std:
       for (int l = i + 1; l < n0; ++l) s -= C[(size_t)l * n0 + i] * Ainv[(size_t)l * n0 + col];
       Ainv[(size_t)i * n0 + col] = s / C[(size_t)i * n0 + i];
     }
+  }
+  return true;
+}
+
+bool coarse_inverse(const Level1D& lv0, int dim, std::vector<double>& Ainv, std::string& err) {
+  const int v[3] = {1, 1, 1};
+  if (!patch_exact_inverse(lv0, dim, v, Ainv, err)) {
+    err = "coarse operator not positive definite";
+    return false;
   }
   return true;
 }

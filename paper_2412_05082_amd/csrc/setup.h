@@ -88,4 +88,11 @@ std::vector<double> prolongation_table(int k);
 // interior nodes, and its inverse (via Cholesky).  Row-major.
 bool coarse_inverse(const Level1D& lv0, int dim, std::vector<double>& Ainv, std::string& err);
 
+// The exact local matrix A_v = R_v A R_v^T of the vertex patch at vertex
+// v[0..dim-1] (each in [1, N-1]) on level lv -- the restriction of the
+// Kronecker form (Sec. 4) to the patch's (2k-1)^dim interior nodes, mixed
+// terms included -- and its inverse (via Cholesky).  Row-major, patch
+// nodes x fastest.  The coarse inverse is the case N = 2, v = (1, ..., 1).
+bool patch_exact_inverse(const Level1D& lv, int dim, const int* v, std::vector<double>& Ainv, std::string& err);
+
 }  // namespace c0ip

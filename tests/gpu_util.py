@@ -173,3 +173,34 @@ def fp32_mvs_floor(dim, k, N, omega):
 
 def fp32_mvs_tol(dim, k, N, omega):
     return max(1e-5, 2.0 * fp32_mvs_floor(dim, k, N, omega))
+
+
+@functools.lru_cache(maxsize=None)
+def exact_ops(dim, k, N):
+    """Oracle operator with the exact local matrices A[I_v, I_v] as patch blocks."""
+    A = O.assemble(dim, k, N)
+    pidx = O.patch_indices(dim, k, N)
+    return A, O.patch_blocks(A, pidx), pidx, O.mvs_colors(dim, N)
+
+
+def fp64_exact_tol(dim, k, N):
+    """1e-12, or 2 kappa(A_v) eps for the exact local matrices."""
+    _, blocks, _, _ = exact_ops(dim, k, min(N, 8))
+    kap = max(np.linalg.cond(blocks[i]) for i in range(0, len(blocks), max(1, len(blocks) // 16)))
+    return max(1e-12, 2.0 * kap * EPS64)
+
+
+@functools.lru_cache(maxsize=None)
+def fp32_exact_floor(dim, k, N, omega):
+    """Float32 floor of an additive step with exact local solves: float32
+    residual, exact (float64) solves, against the float64 step."""
+    N = _small_N(dim, k, N)
+    A, blocks, pidx, _ = exact_ops(dim, k, N)
+    x32, b32 = (v.astype(np.float32) for v in vectors(dim, k, N))
+    x, b = x32.astype(np.float64), b32.astype(np.float64)
+    ref = O.avs_apply(A, blocks, pidx, x, b, omega, 1)
+    r32 = (b32 - A.astype(np.float32) @ x32).astype(np.float64)
+    u = np.linalg.solve(blocks, r32[pidx][..., None])[..., 0]
+    corr = np.zeros_like(x)
+    np.add.at(corr, pidx.ravel(), u.ravel())
+    return rel_l2(x + omega * corr, ref)

@@ -87,6 +87,28 @@ def test_host_fdm_inverse_matches_dense_lu(dim, k, N):
         assert np.linalg.norm(Av @ u - r) <= 1e-12 * np.linalg.norm(r) * max(1.0, kappa / 1e3)
 
 
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 8), (2, 3, 8), (2, 5, 4), (2, 7, 4), (3, 2, 4), (3, 3, 2)])
+def test_host_exact_inverse_matches_oracle_block(dim, k, N):
+    """The exact local solver's inverse (local_solver 1) is the inverse of
+    the oracle's block A[I_v, I_v] of the quadrature-assembled operator, for
+    every boundary type of the patch (Table 1's exact local solvers)."""
+    A = O.assemble(dim, k, N)
+    verts = O.patch_vertices(dim, N)
+    pick = {}
+    for v in verts:
+        key = tuple((1 if vm == 1 else 0) | (2 if vm == N - 1 else 0) for vm in v)
+        pick.setdefault(key, v)
+    for key, v in pick.items():
+        pidx = O.patch_indices(dim, k, N, v[None, :])
+        Av = O.patch_blocks(A, pidx)[0]
+        Ainv = P.host_patch_inverse_exact(dim, k, N, [int(t) for t in v])
+        ref = np.linalg.inv(Av)
+        kappa = np.linalg.cond(Av)
+        assert np.abs(Ainv - ref).max() <= 50 * kappa * 1e-16 * np.abs(ref).max(), (key, kappa)
+        # and it is not the separable inverse (the mixed terms matter)
+        assert np.abs(Ainv - P.host_patch_inverse(dim, k, N, [int(t) for t in v])).max() > 1e-3 * np.abs(ref).max()
+
+
 def test_host_entry_points_reject_bad_arguments():
     with pytest.raises(P.C0ipError) as e:
         P.host_matrices_1d(1, 4)
