@@ -353,6 +353,24 @@ def bench_sweep(args, torch, P):
     for k, N in SWEEP:
         b = torch.from_numpy(seeded_vector(2, k, N, 0)).to(dev)
         row = {"degree": k, "cells": N, "dofs": b.numel()}
+        # kernel rates at this degree (cold buffers: sets > 1 GB in total)
+        n = b.numel()
+        pk = P.Problem(2, N, k, omega=args.omega, vcycle_dtype=P.C0IP_F32)
+        pk.autotune()
+        xk = torch.from_numpy(seeded_vector(2, k, N, 1)).to(dev)
+        nsets = max(4, int(1.2e9 // (3 * 8 * n)) + 1)
+        sets = [(xk.clone(), torch.empty_like(xk), b.clone()) for _ in range(nsets)]
+        reps = max(5, args.reps // 3)
+        ms = {"matvec_f64": time_kernel(lambda st: pk.apply_A(st[0], st[1]), sets, reps, torch),
+              "smoother_f64": time_kernel(lambda st: pk.smoother_step(st[2], st[0], st[1]), sets, reps, torch)}
+        sets = [(st[0].float(), st[1].float(), st[2].float()) for st in sets]
+        ms["smoother_f32"] = time_kernel(lambda st: pk.smoother_step(st[2], st[0], st[1]), sets, reps, torch)
+        row["kernels"] = {kname: {"ms": v, "dofs_per_s": n / (v * 1e-3),
+                                  "alg_GBs": {"matvec_f64": 16, "smoother_f64": 24, "smoother_f32": 12}[kname] * n /
+                                  (v * 1e-3) / 1e9} for kname, v in ms.items()}
+        row["kernels"]["smoother_f32_variant"] = pk.tuned_variant(dtype=P.C0IP_F32)
+        del sets, xk
+        pk.close()
         xs = {}
         for name, dt in [("f32_vcycle", P.C0IP_F32), ("f64_vcycle", P.C0IP_F64)]:
             pb = P.Problem(2, N, k, omega=args.omega, vcycle_dtype=dt)
