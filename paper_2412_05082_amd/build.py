@@ -14,7 +14,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libc0ip.so")
 
-HIP_SOURCES = ["kernels2d.hip", "op2d.hip", "op3d.hip", "smooth3d.hip", "kernels3d.hip", "kernels_common.hip", "api.hip", "batch.hip", "vtail.hip", "krylov_cg.hip", "mvs3d.hip"]
+HIP_SOURCES = ["kernels2d.hip", "op2d.hip", "op2d_avs64.hip", "op2d_avs32.hip", "op3d.hip", "smooth3d.hip", "kernels3d.hip", "kernels_common.hip", "api.hip", "batch.hip", "vtail.hip", "krylov_cg.hip", "mvs3d.hip"]
 CXX_SOURCES = ["setup.cpp"]
 ARCH = os.environ.get("C0IP_OFFLOAD_ARCH", "gfx950")
 # packed FP32 instructions are kept out of every code object

@@ -17,6 +17,7 @@
 #include "exact.h"
 #include "krylov_cg.h"
 #include "mvs3d.h"
+#include "pre2d.h"
 #include "setup.h"
 
 namespace {
@@ -398,19 +399,25 @@ void c0ip_problem::mg_level2d(int l, const T* b, T* x) {
   const T om = (T)mg.omega;
   T* A = (post % 2 == 1) ? w.t.p : x;
   T* B = (A == x) ? w.t.p : x;
-  if (pre == 0) {
-    check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), A, stream), "fill");
+  const bool fused_pre = pre == 1 && Nl <= c0ip::kPre2dMaxN && k <= 3;
+  if (fused_pre) {
+    // x1 = S(0, b) and r = b - A x1 in one launch
+    check(c0ip::launch_pre2d<T>(k, Nl, w.coef, w.eig, b, A, w.r.p, om, stream), "pre-smoother + residual");
   } else {
-    T* cur = (pre % 2 == 1) ? A : B;
-    check(c0ip::launch_patch2d<T>(k, Nl, w.eig, b, nullptr, cur, om, stream), "smoother");
-    for (int s = 1; s < pre; ++s) {
-      T* nxt = (cur == A) ? B : A;
-      check(c0ip::launch_avs2d<T>(k, Nl, w.coef, w.eig, cur, b, nxt, om, stream, 1, 0, nullptr, w.avs_variant),
-            "fused smoother");
-      cur = nxt;
+    if (pre == 0) {
+      check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), A, stream), "fill");
+    } else {
+      T* cur = (pre % 2 == 1) ? A : B;
+      check(c0ip::launch_patch2d<T>(k, Nl, w.eig, b, nullptr, cur, om, stream), "smoother");
+      for (int s = 1; s < pre; ++s) {
+        T* nxt = (cur == A) ? B : A;
+        check(c0ip::launch_avs2d<T>(k, Nl, w.coef, w.eig, cur, b, nxt, om, stream, 1, 0, nullptr, w.avs_variant),
+              "fused smoother");
+        cur = nxt;
+      }
     }
+    check(c0ip::launch_apply2d<T, T>(k, Nl, w.coef, A, b, w.r.p, stream), "residual");
   }
-  check(c0ip::launch_apply2d<T, T>(k, Nl, w.coef, A, b, w.r.p, stream), "residual");
   check(c0ip::launch_restrict2d<T>(k, lv[l - 1]->N, w.ptab.p, w.r.p, wc.b.p, stream), "restrict");
   mg_level<T>(l - 1, wc.b.p, wc.x.p);
   if (post == 0) {

@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "exact.h"
+#include "fdm.h"
 #include "kernels.h"
 #include "tiles.h"
 
@@ -28,6 +29,9 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
                                                            const T* __restrict__ Qg, const T* __restrict__ lamg,
                                                            T omega, int64_t zs, const int* __restrict__ active) {
   constexpr int n = 2 * K - 1, NN = n * n, NP = TC + 1, S = (TC + 2) * K - 1;
+  // small patches (k <= 3): one thread per patch, transforms in registers (for k = 4 this was measured
+  // several times slower than the passes below)
+  constexpr bool REG = NN <= 25;
   if (active && !active[blockIdx.z]) return;
   r += blockIdx.z * zs;
   xout += blockIdx.z * zs;
@@ -35,9 +39,10 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
   constexpr int NL = (S * S + kThreads - 1) / kThreads;
   __shared__ T sR[S * S];
   __shared__ T sA[NP * NP * NN];
-  __shared__ T sB[NP * NP * NN];
+  __shared__ T sB[REG ? 1 : NP * NP * NN];
   __shared__ T sQ[4 * NN];
   __shared__ T sLam[4 * n];
+  __shared__ T sD[NN];
   int tbx, tby;
   xcd_tile(tbx, tby);
   const int cx0 = tbx * TC, cy0 = tby * TC;
@@ -53,6 +58,7 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
     }
     for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
     for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
+    for (int e = threadIdx.x; e < NN; e += kThreads) sD[e] = T(1) / (lamg[e % n] + lamg[e / n]);  // [ap][c]
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       const int e = threadIdx.x + q * kThreads;
@@ -60,6 +66,29 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
     }
   }
   __syncthreads();
+  if constexpr (REG) {
+    // every patch of an interior tile has the interior basis (wave-uniform reads)
+    const bool interior = cx0 >= 2 && cx0 + TC <= N - 2 && cy0 >= 2 && cy0 + TC <= N - 2;
+    for (int p = threadIdx.x; p < NP * NP; p += kThreads) {
+      const int pyl = p / NP, pxl = p - pyl * NP;
+      const int vx = cx0 + pxl, vy = cy0 + pyl;
+      if (vx < 1 || vx > N - 1 || vy < 1 || vy > N - 1) continue;
+      const T* src = sR + (pyl * K) * S + pxl * K;
+      if (interior) {
+        fdm::patch_reg<T, n>(src, S, sA + p * NN, [&](int i) { return Qg[i]; }, [&](int i) { return Qg[i]; },
+                             [&](int ap, int c) { return sD[ap * n + c]; });
+      } else {
+        const int tx = variant(vx, N), ty = variant(vy, N);
+        const T* qx = sQ + tx * NN;
+        const T* qy = sQ + ty * NN;
+        const T* lx = sLam + tx * n;
+        const T* ly = sLam + ty * n;
+        fdm::patch_reg<T, n>(src, S, sA + p * NN, [&](int i) { return qx[i]; }, [&](int i) { return qy[i]; },
+                             [&](int ap, int c) { return T(1) / (lx[c] + ly[ap]); });
+      }
+    }
+    __syncthreads();
+  } else {
   const T* Q = sQ;
   const T* lam = sLam;
   // forward along x: t[a][c] = sum_c' Qx[c'][c] r[a][c']
@@ -128,6 +157,7 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
     }
   }
   __syncthreads();
+  }
   // owned DoFs: sum the covering patches' corrections
   constexpr int OW = TC * K + 1;
   const int gx0 = cx0 * K, gy0 = cy0 * K;
@@ -159,8 +189,8 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
 }
 
 template <int K> struct PatchTile2D;
-template <> struct PatchTile2D<2> { static constexpr int TC = 16; };
-template <> struct PatchTile2D<3> { static constexpr int TC = 8; };
+template <> struct PatchTile2D<2> { static constexpr int TC = 15; };  // 256 patches: one per thread
+template <> struct PatchTile2D<3> { static constexpr int TC = 15; };
 template <> struct PatchTile2D<4> { static constexpr int TC = 8; };
 template <> struct PatchTile2D<5> { static constexpr int TC = 4; };
 template <> struct PatchTile2D<6> { static constexpr int TC = 4; };

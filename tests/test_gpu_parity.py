@@ -351,7 +351,8 @@ def test_vcycle_smoothing_steps(pre, post):
     check("vcycle f64 steps", rel_l2(host(xd), ref), fp64_vcycle_tol(dim, k, N, pre, post))
 
 
-@pytest.mark.parametrize("k,N", [(2, 64), (3, 64), (3, 32), (4, 16), (4, 32), (5, 8), (5, 16), (6, 8), (7, 8)])
+@pytest.mark.parametrize("k,N", [(2, 64), (3, 64), (3, 32), (4, 16), (4, 32), (5, 8), (5, 16), (6, 8), (6, 16), (7, 8),
+                                 (7, 16)])
 @pytest.mark.parametrize("dtype", [P.C0IP_F64, P.C0IP_F32])
 def test_every_fused_tile_variant_and_autotune(k, N, dtype):
     """Each compiled tile size of the fused smoother gives the oracle's
