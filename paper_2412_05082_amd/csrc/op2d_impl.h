@@ -21,7 +21,6 @@
 // the scalar budget is applied in groups of cell positions.  Boundary tiles
 // read per-lane row classes from the global table.
 #include <algorithm>
-#include <cstdlib>
 
 #include "fdm.h"
 #include "kernels.h"
@@ -47,10 +46,9 @@ constexpr int group_end(int p0) {
 
 // Tile geometry: TXC x TYC cells, NTH threads, x items of CW cells, y items
 // of RW cell rows.
-template <int K_, int TXC_, int TYC_, int NTH_, int CW_, int RW_, bool OP3_ = false>
+template <int K_, int TXC_, int TYC_, int NTH_, int CW_, int RW_>
 struct Geo {
   static constexpr int K = K_, TXC = TXC_, TYC = TYC_, NTH = NTH_, CW = CW_, RW = RW_;
-  static constexpr bool OP3 = OP3_;  // the three terms through one x pass into three LDS buffers
   static constexpr int H = 2 * K, TX = TXC * K, TY = TYC * K, RX = TX + 2 * H, RY = TY + 2 * H, W = 4 * K + 1;
   static constexpr int NIT_Y = TX * (TYC / RW), NI = (NIT_Y + NTH - 1) / NTH;
   static constexpr int TABMAX = 3 * (5 * K + 2) * W;  // row classes: at most 5k+2
@@ -155,126 +153,6 @@ __device__ __forceinline__ void op_tile(const T* __restrict__ sX, T* __restrict_
   ypass_all<T, G, 2, 0, YIN, false>(sT, acc, T(1), tab, sTab, nclass, left, right0, periodic, y0, n1);
 }
 
-// The three Kronecker terms with one x pass and one y pass: the x pass loads
-// each input window once and writes X B_x, X L_x (rows [K, RY - K), where the
-// M_y and L_y bands reach) and X M_x (every staged row) to three LDS buffers;
-// the y pass then accumulates M_y (X B_x) + 2 L_y (X L_x) + B_y (X M_x).  Two
-// barriers instead of six, a third of the x-pass LDS reads, three times the
-// LDS buffer.  Cell positions are grouped so that the three factors' bands of
-// a group fit the scalar budget.
-template <typename T, int K>
-constexpr int group3_end(int p0) {
-  constexpr int budget = sizeof(T) == 8 ? 40 : 80;
-  int s = 0, p = p0;
-  while (p < K && s + Band<0, K>::width(p) + Band<1, K>::width(p) + Band<2, K>::width(p) <= budget)
-    s += Band<0, K>::width(p) + Band<1, K>::width(p) + Band<2, K>::width(p), ++p;
-  return p == p0 ? p0 + 1 : p;
-}
-
-template <typename T, class G, int P0, int P1, bool XIN>
-__device__ __forceinline__ void xpass3(const T* __restrict__ sX, T* __restrict__ sTB, T* __restrict__ sTL,
-                                       T* __restrict__ sTM, const T* __restrict__ tab, const T* __restrict__ sTab,
-                                       int nclass, int left, int right0, int periodic, int x0, int n1) {
-  constexpr int K = G::K, CW = G::CW, H = G::H, RY = G::RY;
-  constexpr int NG = G::TXC / CW;
-  constexpr int LO = Band<2, K>::win_lo(P0), HI = Band<2, K>::win_hi() + (CW - 1) * K;
-  for (int it = threadIdx.x; it < RY * NG; it += G::NTH) {
-    const int r = it / NG, g = it - r * NG;
-    T in[HI - LO + 1];
-#pragma unroll
-    for (int j = LO; j <= HI; ++j) in[j - LO] = sX[r * G::RX + g * CW * K + j];
-    const bool mid = r >= K && r < RY - K;
-#pragma unroll
-    for (int p = P0; p < P1; ++p) {
-#pragma unroll
-      for (int w = 0; w < CW; ++w) {
-        const int cl = XIN ? 2 * left + p
-                           : tile::row_class(clampi(x0 + (g * CW + w) * K + p, 0, n1 - 1), n1, K, left, right0,
-                                             periodic);
-        const T* v = in + (w * K + p + H - LO);
-        const int o = r * G::TX + (g * CW + w) * K + p;
-        sTM[o] = band_row<T, 0, K, XIN>(tab, sTab, nclass, left, periodic, cl, v, p);
-        if (mid) {
-          sTB[o] = band_row<T, 2, K, XIN>(tab, sTab, nclass, left, periodic, cl, v, p);
-          sTL[o] = band_row<T, 1, K, XIN>(tab, sTab, nclass, left, periodic, cl, v, p);
-        }
-      }
-    }
-  }
-}
-
-template <typename T, class G, int P0, bool XIN>
-__device__ __forceinline__ void xpass3_all(const T* __restrict__ sX, T* __restrict__ sTB, T* __restrict__ sTL,
-                                           T* __restrict__ sTM, const T* __restrict__ tab,
-                                           const T* __restrict__ sTab, int nclass, int left, int right0,
-                                           int periodic, int x0, int n1) {
-  constexpr int P1 = group3_end<T, G::K>(P0);
-  xpass3<T, G, P0, P1, XIN>(sX, sTB, sTL, sTM, tab, sTab, nclass, left, right0, periodic, x0, n1);
-  if constexpr (P1 < G::K)
-    xpass3_all<T, G, P1, XIN>(sX, sTB, sTL, sTM, tab, sTab, nclass, left, right0, periodic, x0, n1);
-}
-
-template <typename T, class G, int P0, int P1, bool YIN, bool SET>
-__device__ __forceinline__ void ypass3(const T* __restrict__ sTB, const T* __restrict__ sTL,
-                                       const T* __restrict__ sTM, T (&acc)[G::NI][G::RW * G::K],
-                                       const T* __restrict__ tab, const T* __restrict__ sTab, int nclass, int left,
-                                       int right0, int periodic, int y0, int n1) {
-  constexpr int K = G::K, RW = G::RW, H = G::H, TX = G::TX;
-  constexpr int LOM = Band<0, K>::win_lo(P0), HIM = Band<0, K>::win_hi() + (RW - 1) * K;
-  constexpr int LOB = Band<2, K>::win_lo(P0), HIB = Band<2, K>::win_hi() + (RW - 1) * K;
-#pragma unroll
-  for (int q = 0; q < G::NI; ++q) {
-    const int it = threadIdx.x + q * G::NTH;
-    if (G::NIT_Y % G::NTH != 0 && it >= G::NIT_Y) break;
-    const int cg = it / TX, l = it - cg * TX;
-    T tb[HIM - LOM + 1], tl[HIM - LOM + 1], tm[HIB - LOB + 1];
-#pragma unroll
-    for (int j = LOM; j <= HIM; ++j) {
-      tb[j - LOM] = sTB[(cg * RW * K + j) * TX + l];
-      tl[j - LOM] = sTL[(cg * RW * K + j) * TX + l];
-    }
-#pragma unroll
-    for (int j = LOB; j <= HIB; ++j) tm[j - LOB] = sTM[(cg * RW * K + j) * TX + l];
-#pragma unroll
-    for (int p = P0; p < P1; ++p) {
-#pragma unroll
-      for (int w = 0; w < RW; ++w) {
-        const int cl = YIN ? 2 * left + p
-                           : tile::row_class(clampi(y0 + (cg * RW + w) * K + p, 0, n1 - 1), n1, K, left, right0,
-                                             periodic);
-        const T a = band_row<T, 0, K, YIN>(tab, sTab, nclass, left, periodic, cl, tb + (w * K + p + H - LOM), p) +
-                    T(2) * band_row<T, 1, K, YIN>(tab, sTab, nclass, left, periodic, cl, tl + (w * K + p + H - LOM), p) +
-                    band_row<T, 2, K, YIN>(tab, sTab, nclass, left, periodic, cl, tm + (w * K + p + H - LOB), p);
-        acc[q][w * K + p] = a;
-      }
-    }
-  }
-}
-
-template <typename T, class G, int P0, bool YIN>
-__device__ __forceinline__ void ypass3_all(const T* __restrict__ sTB, const T* __restrict__ sTL,
-                                           const T* __restrict__ sTM, T (&acc)[G::NI][G::RW * G::K],
-                                           const T* __restrict__ tab, const T* __restrict__ sTab, int nclass,
-                                           int left, int right0, int periodic, int y0, int n1) {
-  constexpr int P1 = group3_end<T, G::K>(P0);
-  ypass3<T, G, P0, P1, YIN, true>(sTB, sTL, sTM, acc, tab, sTab, nclass, left, right0, periodic, y0, n1);
-  if constexpr (P1 < G::K)
-    ypass3_all<T, G, P1, YIN>(sTB, sTL, sTM, acc, tab, sTab, nclass, left, right0, periodic, y0, n1);
-}
-
-// acc = (A X) on the tile's output nodes through the three-buffer passes
-// (sT3: 3 RY TX entries); ends after the y pass (no barrier).
-template <typename T, class G, bool XIN, bool YIN>
-__device__ __forceinline__ void op_tile3(const T* __restrict__ sX, T* __restrict__ sT3,
-                                         T (&acc)[G::NI][G::RW * G::K], const T* __restrict__ tab,
-                                         const T* __restrict__ sTab, int nclass, int left, int right0, int periodic,
-                                         int x0, int y0, int n1) {
-  constexpr int NT = G::RY * G::TX;
-  xpass3_all<T, G, 0, XIN>(sX, sT3, sT3 + NT, sT3 + 2 * NT, tab, sTab, nclass, left, right0, periodic, x0, n1);
-  __syncthreads();
-  ypass3_all<T, G, 0, YIN>(sT3, sT3 + NT, sT3 + 2 * NT, acc, tab, sTab, nclass, left, right0, periodic, y0, n1);
-}
-
 template <class G>
 __device__ __forceinline__ bool tile_xin(int periodic, int left, int right0, int x0) {
   return periodic && x0 >= left && x0 + G::TX <= right0;
@@ -305,22 +183,6 @@ __device__ __forceinline__ void op_tile_any(const T* __restrict__ sX, T* __restr
     op_tile<T, G, false, true>(sX, sT, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
   else
     op_tile<T, G, false, false>(sX, sT, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
-}
-
-template <typename T, class G>
-__device__ __forceinline__ void op_tile3_any(const T* __restrict__ sX, T* __restrict__ sT3,
-                                             T (&acc)[G::NI][G::RW * G::K], const T* __restrict__ tab,
-                                             const T* __restrict__ sTab, int nclass, int left, int right0,
-                                             int periodic, int x0, int y0, int n1) {
-  const bool xin = tile_xin<G>(periodic, left, right0, x0), yin = tile_yin<G>(periodic, left, right0, y0);
-  if (xin && yin)
-    op_tile3<T, G, true, true>(sX, sT3, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
-  else if (xin)
-    op_tile3<T, G, true, false>(sX, sT3, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
-  else if (yin)
-    op_tile3<T, G, false, true>(sX, sT3, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
-  else
-    op_tile3<T, G, false, false>(sX, sT3, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
 }
 
 // Stage X on [x0 - 2k, x0 + TX + 2k) x [y0 - 2k, y0 + TY + 2k) (zero outside the mesh).
@@ -354,7 +216,7 @@ __global__ __launch_bounds__(G::NTH) void apply2d_kernel(const Tin* __restrict__
   y += blockIdx.z * zs;
   if (RES) b += blockIdx.z * zs;
   __shared__ T sX[G::RY * G::RX];
-  __shared__ T sT[(G::OP3 ? 3 : 1) * G::RY * G::TX];
+  __shared__ T sT[G::RY * G::TX];
   __shared__ T sTab[G::TABMAX];
   const int x0 = bx * G::TX, y0 = by * G::TY;
   stage_x<Tin, T, G>(x, sX, x0, y0, n1);
@@ -378,10 +240,7 @@ __global__ __launch_bounds__(G::NTH) void apply2d_kernel(const Tin* __restrict__
   }
   T acc[G::NI][G::RW * G::K];
   __syncthreads();
-  if constexpr (G::OP3)
-    op_tile3_any<T, G>(sX, sT, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
-  else
-    op_tile_any<T, G>(sX, sT, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
+  op_tile_any<T, G>(sX, sT, acc, tab, sTab, nclass, left, right0, periodic, x0, y0, n1);
 #pragma unroll
   for (int q = 0; q < G::NI; ++q) {
     const int it = threadIdx.x + q * G::NTH;
@@ -442,30 +301,13 @@ hipError_t apply2d_g(int n1, const LevelCoef<T>& c, const Tin* x, const T* b, T*
   return hipGetLastError();
 }
 
-template <class G>
-using Op3 = Geo<G::K, G::TXC, G::TYC, G::NTH, G::CW, G::RW, true>;
-
-inline int op3_mode() {
-  static const int m = [] {
-    const char* e = std::getenv("C0IP_OP3");
-    return e ? std::atoi(e) : 0;
-  }();
-  return m;
-}
-
 template <typename Tin, typename T, int K>
 hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s, int nsys,
                      int64_t zs, const int* active) {
   using G = typename ApplyCfg<K>::G;
-  using GS = typename ApplyCfgSmall<K>::G;
   const int n1 = K * N + 1;
   const int64_t big = (int64_t)((n1 + G::TX - 1) / G::TX) * ((n1 + G::TY - 1) / G::TY) * nsys;
-  const int m = op3_mode();
-  if (big < 256) {
-    if (m & 2) return apply2d_g<Tin, T, Op3<GS>>(n1, c, x, b, y, s, nsys, zs, active);
-    return apply2d_g<Tin, T, GS>(n1, c, x, b, y, s, nsys, zs, active);
-  }
-  if (m & 1) return apply2d_g<Tin, T, Op3<G>>(n1, c, x, b, y, s, nsys, zs, active);
+  if (big < 256) return apply2d_g<Tin, T, typename ApplyCfgSmall<K>::G>(n1, c, x, b, y, s, nsys, zs, active);
   return apply2d_g<Tin, T, G>(n1, c, x, b, y, s, nsys, zs, active);
 }
 
