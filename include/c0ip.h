@@ -232,10 +232,15 @@ c0ip_status c0ip_solve_fcg(c0ip_problem* p, const c0ip_krylov_opts* opts, const 
  * (shared damping, steps and precision).  Systems of equal degree and
  * penalty share every V-cycle launch of a level (all their meshes have
  * 2^(l+1) cells there), the Krylov kernels take per-system descriptors, and
- * each round -- one Arnoldi step of every unconverged system -- is a single
- * replay of a captured HIP graph; converged systems are masked off on the
- * device.  dim must be 2 (C0IP_EUNSUPPORTED otherwise).  hip_stream: the
- * caller's stream (NULL = default); the batch orders its work after it. */
+ * each round -- one Arnoldi step of every active system, ending in its
+ * Givens step on the device -- is a single replay of a captured HIP graph.
+ * The device keeps every system's Krylov state: it advances a system, or
+ * stops it (converged, basis full, max_iters) and masks it off; rounds are
+ * queued back to back, and the host reads each round's state two rounds
+ * later, queueing x += Z y and the restart of a stopped system behind the
+ * rounds in flight.  dim must be 2 (C0IP_EUNSUPPORTED otherwise).
+ * hip_stream: the caller's stream (NULL = default); the batch orders its
+ * work after it. */
 typedef struct c0ip_batch c0ip_batch; /* opaque; owned by the library */
 c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, int n_problems,
                               const c0ip_mg_opts* opts, void* hip_stream, c0ip_batch** out);

@@ -1,6 +1,11 @@
 // Batched solves: many independent systems (problems x right-hand sides,
 // uneven sizes and degrees) advance one flexible-GMRES step per round, and
-// every round is one replay of a captured HIP graph.
+// every round is one replay of a captured HIP graph.  The Krylov state of
+// every system lives on the device: the round's last kernel runs the Givens
+// step, advances the system or stops it, so rounds follow one another with
+// no host work in between; the host only reads each round's state (copied
+// out by the graph) a few rounds later and queues the solution update and
+// restart of the systems that stopped.
 //
 // Systems are grouped by (k, gamma); within a group they are ordered by
 // decreasing number of levels L_s, so at level l the systems still present
@@ -10,7 +15,7 @@
 // system enters the V-cycle at its own finest level on the way down and
 // leaves there on the way up (Algorithm 1 for each system).  Converged
 // systems are masked off on the device, so the graph never changes.
-// The Krylov kernels take per-system descriptors (sizes differ).
+// The Krylov kernels take per-system state records (sizes differ).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,25 +37,36 @@ constexpr int kPer = 8;                 // entries per lane in the dot kernel
 constexpr int kChunk = kThreads * kPer;  // entries per dot block
 constexpr int kVec = 4;
 constexpr int kMaxM = 64;
+constexpr int kRing = 3;      // round graphs (and state snapshots) in rotation
+constexpr int kInFlight = 2;  // rounds queued ahead of the host's reading of the state
 
-struct KrySys {  // one system's Krylov state on the device (host rewrites it every round)
-  double* V;
-  double* u;
-  const double* w;
+// Where a system stands between rounds.  The host writes the state once per
+// solve; after that only the device changes it: the Givens kernel advances j
+// or stops the system, the restart kernel re-activates it.
+// kExact: the residual met at a restart is exactly zero (converged, x final).
+enum : int { kRun = 0, kRestart = 1, kConverged = 2, kMaxIts = 3, kFailed = 4, kExact = 5 };
+
+struct KrySys {
+  double* V;         // m basis vectors, n apart
+  double* u;         // current (unnormalised) Krylov vector
+  const double* w;   // A z of the round
+  void* Z;           // m preconditioned vectors (V-cycle precision), n apart
+  void* vin;         // the V-cycle's right-hand-side slot
+  const void* vout;  // the V-cycle's solution slot
+  int* mask;         // this system's entry in its group's activity mask
+  double* H;         // (m + 1) x m Hessenberg matrix, row-major
+  double* y;         // m coefficients of the update x += Z y
   int64_t n;
   int64_t poff;  // offset of its partial sums
-  int j;
-  int active;
   int nblk;
-  int pad;
+  // changed on the device
+  int j, its, status, active, epoch;
+  double bnorm, beta, g0, last;
 };
 
-struct CopyDesc {  // dst[i] = src[i], with the element types of mode
-  const void* src;
-  void* dst;
-  int64_t n;
-  int mode;  // 0 f64->f64, 1 f64->f32, 2 f32->f32
-  int active;
+struct KryParams {  // options of the running solve (read by the Givens kernel)
+  double rtol;
+  int max_iters;
 };
 
 __device__ __forceinline__ double wsum(double v) {
@@ -206,17 +222,163 @@ __global__ __launch_bounds__(kThreads) void bupdate_kernel(const KrySys* __restr
   }
 }
 
-__global__ __launch_bounds__(kThreads) void bcopy_kernel(const CopyDesc* __restrict__ desc) {
-  const CopyDesc d = desc[blockIdx.y];
+// One Givens step per system (one workgroup each).  The round's reductions
+// complete column j-1 of H (delayed re-orthogonalisation) and give column j,
+// with h_{j+1,j} from Pythagoras (the explicit norm of the new u under heavy
+// cancellation).  The QR factorisation of H by Givens rotations, applied to
+// g0 e_1, gives the residual estimate |g_{j+1}|.  A system that converges,
+// fills its basis or reaches max_iters leaves y = R^{-1} g for x += Z y and
+// goes idle; otherwise it moves on to j + 1.  The arithmetic and its order
+// are those of the single-system solve.
+__global__ __launch_bounds__(kThreads) void bgivens_kernel(KrySys* __restrict__ sys, int m,
+                                                           const double* __restrict__ hout,
+                                                           const double* __restrict__ coef,
+                                                           const KryParams* __restrict__ prm) {
+  KrySys* ds = sys + blockIdx.x;
+  const KrySys d = *ds;
   if (!d.active) return;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads) {
-    if (d.mode == 0)
-      ((double*)d.dst)[i] = ((const double*)d.src)[i];
-    else if (d.mode == 1)
-      ((float*)d.dst)[i] = (float)((const double*)d.src)[i];
-    else
-      ((float*)d.dst)[i] = ((const float*)d.src)[i];
+  __shared__ double R[(kMaxM + 1) * kMaxM];
+  __shared__ double g[kMaxM + 1];
+  __shared__ double rot[2];
+  __shared__ double red[kThreads / 64];
+  __shared__ double est_s;
+  const int t = threadIdx.x, j = d.j, nc = j + 1, nr = j + 2;
+  const double* h = hout + (int64_t)blockIdx.x * (2 * m + 3);
+  const double* cf = coef + (int64_t)blockIdx.x * (2 * m + 5);
+  const double alpha = cf[2 * j + 2], hv = cf[2 * j + 3], ww = h[2 * j + 2];
+  if (!isfinite(alpha) || !isfinite(hv) || !isfinite(ww)) {
+    if (t == 0) {
+      ds->status = kFailed;
+      ds->active = 0;
+      *d.mask = 0;
+    }
+    return;
   }
+  // columns 0..j of H with this round's entries, rows 0..j+1, into LDS
+  for (int e = t; e < nr * nc; e += kThreads) {
+    const int r = e / nc, c = e - r * nc;
+    double v;
+    if (c < j - 1)
+      v = d.H[(int64_t)r * m + c];
+    else if (c == j - 1)
+      v = r < j ? d.H[(int64_t)r * m + c] + h[r] : (r == j ? alpha : 0.0);
+    else
+      v = r < j ? h[j + r] : (r == j ? hv : 0.0);
+    R[e] = v;
+  }
+  if (t == 0) {
+    double c2 = 0;
+    for (int i = 0; i < j; ++i) c2 += h[j + i] * h[j + i];
+    est_s = ww - c2 - hv * hv;
+  }
+  __syncthreads();
+  double est2 = est_s;
+  if (!(est2 > 1e-10 * ww)) {  // heavy cancellation: exact norm
+    double sum = 0;
+    for (int64_t i = t; i < d.n; i += kThreads) sum += d.u[i] * d.u[i];
+    sum = wsum(sum);
+    if ((t & 63) == 0) red[t >> 6] = sum;
+    __syncthreads();
+    est2 = 0;
+    for (int q = 0; q < kThreads / 64; ++q) est2 += red[q];
+  }
+  const double hn = sqrt(fmax(est2, 0.0));
+  const double g0 = j == 0 ? d.beta * alpha : d.g0;  // r = beta u = beta alpha V_0
+  if (t == 0) {
+    R[(j + 1) * nc + j] = hn;
+    g[0] = g0;
+    for (int r = 1; r < nr; ++r) g[r] = 0.0;
+  }
+  __syncthreads();
+  // the completed column j-1 and the new column j back to H
+  for (int r = t; r < nr; r += kThreads) {
+    if (j > 0) d.H[(int64_t)r * m + j - 1] = R[r * nc + j - 1];
+    d.H[(int64_t)r * m + j] = R[r * nc + j];
+  }
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    if (t == 0) {
+      const double a = R[c * nc + c], b = R[(c + 1) * nc + c];
+      const double den = hypot(a, b);
+      const double cs = den > 0 ? a / den : 1.0, sn = den > 0 ? b / den : 0.0;
+      rot[0] = cs;
+      rot[1] = sn;
+      const double x = g[c], y = g[c + 1];
+      g[c] = cs * x + sn * y;
+      g[c + 1] = -sn * x + cs * y;
+    }
+    __syncthreads();
+    const double cs = rot[0], sn = rot[1];
+    for (int cc = c + t; cc < nc; cc += kThreads) {
+      const double x = R[c * nc + cc], y = R[(c + 1) * nc + cc];
+      R[c * nc + cc] = cs * x + sn * y;
+      R[(c + 1) * nc + cc] = -sn * x + cs * y;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double res = fabs(g[nr - 1]);
+    const int its = d.its + 1;
+    const bool conv = res <= prm->rtol * d.bnorm || hn == 0.0;
+    ds->its = its;
+    ds->last = res;
+    ds->g0 = g0;
+    if (conv || j + 1 == m || its >= prm->max_iters) {
+      for (int i = nc - 1; i >= 0; --i) {  // y = R^{-1} g, into LDS row g
+        double v = g[i];
+        for (int l2 = i + 1; l2 < nc; ++l2) v -= R[i * nc + l2] * g[l2];
+        g[i] = v / R[i * nc + i];
+      }
+      for (int i = 0; i < nc; ++i) d.y[i] = g[i];
+      ds->status = conv ? kConverged : (its >= prm->max_iters ? kMaxIts : kRestart);
+      ds->active = 0;
+      *d.mask = 0;
+    } else {
+      ds->j = j + 1;
+    }
+  }
+}
+
+// A system that stopped, after x += Z y and r = b - A x: beta = ||r||; one
+// that only filled its basis (and has u = r / beta) starts its next cycle.
+__global__ __launch_bounds__(kThreads) void brestart_kernel(KrySys* __restrict__ ds, int m,
+                                                            const double* __restrict__ nrm2) {
+  const KrySys d = *ds;
+  const double beta = sqrt(nrm2[0]);
+  const bool again = d.status == kRestart && isfinite(beta) && beta > 0;
+  if (again)
+    for (int e = threadIdx.x; e < (m + 1) * m; e += kThreads) d.H[e] = 0.0;
+  if (threadIdx.x == 0) {
+    ds->beta = beta;
+    ds->epoch = d.epoch + 1;
+    if (again) {
+      ds->j = 0;
+      ds->status = kRun;
+      ds->active = 1;
+      *d.mask = 1;
+    } else if (d.status == kRestart) {
+      ds->status = isfinite(beta) ? kExact : kFailed;
+    }
+  }
+}
+
+template <typename Tv>
+__global__ __launch_bounds__(kThreads) void bcopy_in_kernel(const KrySys* __restrict__ sys) {
+  const KrySys d = sys[blockIdx.y];
+  if (!d.active) return;
+  Tv* dst = (Tv*)d.vin;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads)
+    dst[i] = (Tv)d.u[i];
+}
+
+template <typename Tz>
+__global__ __launch_bounds__(kThreads) void bcopy_out_kernel(const KrySys* __restrict__ sys) {
+  const KrySys d = sys[blockIdx.y];
+  if (!d.active) return;
+  const Tz* src = (const Tz*)d.vout;
+  Tz* dst = (Tz*)d.Z + (int64_t)d.j * d.n;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads)
+    dst[i] = src[i];
 }
 
 int blocks_for(int64_t n) {
@@ -270,12 +432,8 @@ struct Sys {  // one (problem, right-hand side)
   Buf<double> V, u, r;
   Buf<double> Z64;
   Buf<float> Z32;
-  // host FGMRES state
-  std::vector<double> H;
-  double bnorm = 0, beta = 0, g0 = 0, last = 0;
-  int j = 0, its = 0, jdone = 0;
-  bool active = true, converged = false, failed = false;
-  double t_done = 0;
+  Buf<double> H, y;  // Hessenberg matrix and update coefficients (device)
+  double bnorm = 0;
 };
 
 struct Group {
@@ -302,32 +460,34 @@ struct c0ip_batch {
   std::vector<int> nrhs;
   std::vector<c0ip_mesh_desc> meshes;
   int m = 0;
-  int64_t partial_total = 0;
   Buf<KrySys> dsys;
-  Buf<CopyDesc> dcin, dcout;
-  Buf<double> partial, hout, coef, ydev;
-  double* hpin = nullptr;
-  KrySys* hsys = nullptr;
-  CopyDesc *hcin = nullptr, *hcout = nullptr;
-  int* hmask = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  Buf<KryParams> dprm;
+  Buf<double> partial, hout, coef, scal;
+  KrySys* hsys = nullptr;  // pinned: the solve's initial state, then the final one
+  KrySys* hsnap = nullptr;  // pinned: kRing snapshots of the state, one per round in flight
+  KryParams* hprm = nullptr;
+  double* hscal = nullptr;
+  hipGraph_t graph[kRing] = {};
+  hipGraphExec_t exec[kRing] = {};
+  hipEvent_t ev[kRing] = {};
   int graph_m = -1;
   ~c0ip_batch() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int i = 0; i < kRing; ++i) {
+      if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+    }
     for (auto& g : groups) c0ip_destroy(g.proto);
-    if (hpin) (void)hipHostFree(hpin);
     if (hsys) (void)hipHostFree(hsys);
-    if (hcin) (void)hipHostFree(hcin);
-    if (hcout) (void)hipHostFree(hcout);
-    if (hmask) (void)hipHostFree(hmask);
+    if (hsnap) (void)hipHostFree(hsnap);
+    if (hprm) (void)hipHostFree(hprm);
+    if (hscal) (void)hipHostFree(hscal);
     if (s) (void)hipStreamDestroy(s);
   }
 
   template <typename T>
   void vcycle(Group& g);
-  void record_round();
+  void record_round(int slot);
 };
 
 template <typename T>
@@ -431,9 +591,10 @@ void c0ip_batch::vcycle(Group& g) {
   }
 }
 
-// One round for every system: V-cycle inputs, V-cycles, z -> Z_j, A z,
-// one reduction, coefficients, copy of the reductions to the host, update.
-void c0ip_batch::record_round() {
+// One round for every active system: V-cycle inputs, V-cycles, z -> Z_j,
+// A z, one reduction, coefficients, the basis update, the Givens step, and a
+// copy of every system's state to the host (snapshot slot `slot`).
+void c0ip_batch::record_round(int slot) {
   const int ns = (int)sys.size();
   const bool f32 = mg.vcycle_dtype == C0IP_F32;
   int64_t nmax = 0;
@@ -442,7 +603,11 @@ void c0ip_batch::record_round() {
     nmax = std::max(nmax, q.n);
     maxblk = std::max(maxblk, (int)((q.n + kChunk - 1) / kChunk));
   }
-  bcopy_kernel<<<dim3(blocks_for(nmax), ns), kThreads, 0, s>>>(dcin.p);
+  const dim3 grid(blocks_for(nmax), ns);
+  if (f32)
+    bcopy_in_kernel<float><<<grid, kThreads, 0, s>>>(dsys.p);
+  else
+    bcopy_in_kernel<double><<<grid, kThreads, 0, s>>>(dsys.p);
   hchk(hipGetLastError(), "copy in");
   for (auto& g : groups) {
     if (f32)
@@ -450,7 +615,10 @@ void c0ip_batch::record_round() {
     else
       vcycle<double>(g);
   }
-  bcopy_kernel<<<dim3(blocks_for(nmax), ns), kThreads, 0, s>>>(dcout.p);
+  if (f32)
+    bcopy_out_kernel<float><<<grid, kThreads, 0, s>>>(dsys.p);
+  else
+    bcopy_out_kernel<double><<<grid, kThreads, 0, s>>>(dsys.p);
   hchk(hipGetLastError(), "copy out");
   for (auto& g : groups) {
     for (int l = 1; l <= g.Lmax; ++l) {
@@ -475,36 +643,11 @@ void c0ip_batch::record_round() {
   hchk(hipGetLastError(), "reduce");
   bcoef_kernel<<<(ns + 63) / 64, 64, 0, s>>>(dsys.p, ns, m, hout.p, coef.p);
   hchk(hipGetLastError(), "coef");
-  hchk(hipMemcpyAsync(hpin, hout.p, sizeof(double) * ns * (2 * m + 3), hipMemcpyDeviceToHost, s), "D2H");
-  hchk(hipMemcpyAsync(hpin + (size_t)ns * (2 * m + 3), coef.p, sizeof(double) * ns * (2 * m + 5),
-                      hipMemcpyDeviceToHost, s),
-       "D2H");
-  bupdate_kernel<<<dim3(blocks_for(nmax), ns), kThreads, 0, s>>>(dsys.p, m, coef.p);
+  bupdate_kernel<<<grid, kThreads, 0, s>>>(dsys.p, m, coef.p);
   hchk(hipGetLastError(), "update");
-}
-
-static double lsq(const std::vector<double>& H, int m, int j, double g0, std::vector<double>& R,
-                  std::vector<double>& g) {
-  const int nr = j + 2, nc = j + 1;
-  R.assign((size_t)nr * nc, 0.0);
-  for (int r = 0; r < nr; ++r)
-    for (int c = 0; c < nc; ++c) R[(size_t)r * nc + c] = H[(size_t)r * m + c];
-  g.assign(nr, 0.0);
-  g[0] = g0;
-  for (int c = 0; c < nc; ++c) {
-    const double a = R[(size_t)c * nc + c], b = R[(size_t)(c + 1) * nc + c];
-    const double den = std::hypot(a, b);
-    const double cs = den > 0 ? a / den : 1.0, sn = den > 0 ? b / den : 0.0;
-    for (int cc = c; cc < nc; ++cc) {
-      const double x = R[(size_t)c * nc + cc], y = R[(size_t)(c + 1) * nc + cc];
-      R[(size_t)c * nc + cc] = cs * x + sn * y;
-      R[(size_t)(c + 1) * nc + cc] = -sn * x + cs * y;
-    }
-    const double x = g[c], y = g[c + 1];
-    g[c] = cs * x + sn * y;
-    g[c + 1] = -sn * x + cs * y;
-  }
-  return std::fabs(g[nr - 1]);
+  bgivens_kernel<<<ns, kThreads, 0, s>>>(dsys.p, m, hout.p, coef.p, dprm.p);
+  hchk(hipGetLastError(), "givens");
+  hchk(hipMemcpyAsync(hsnap + (size_t)slot * ns, dsys.p, sizeof(KrySys) * ns, hipMemcpyDeviceToHost, s), "D2H");
 }
 
 extern "C" {
@@ -656,11 +799,11 @@ c0ip_status c0ip_batch_solve(c0ip_batch* bt, const c0ip_krylov_opts* opts, const
   hipStream_t s = bt->s;
   auto t0 = std::chrono::steady_clock::now();
   c0ip_status result = C0IP_OK;
+  hipEvent_t ev = nullptr;
   try {
     for (int i = 0; i < (int)bt->meshes.size(); ++i)
       if (!b[i] || !x[i]) return bfail(C0IP_EINVAL, "NULL vector in batch");
     // order after the caller's pending work
-    hipEvent_t ev;
     hchk(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
     hchk(hipEventRecord(ev, bt->user), "event");
     hchk(hipStreamWaitEvent(s, ev, 0), "wait");
@@ -675,216 +818,188 @@ c0ip_status c0ip_batch_solve(c0ip_batch* bt, const c0ip_krylov_opts* opts, const
       q.r.alloc(q.n);
       if (f32) q.Z32.alloc((size_t)m * q.n);
       else q.Z64.alloc((size_t)m * q.n);
-      q.H.assign((size_t)(m + 1) * m, 0.0);
-      const int nblk = (int)((q.n + kChunk - 1) / kChunk);
-      poff += (int64_t)(2 * m + 3) * nblk;
+      q.H.alloc((size_t)(m + 1) * m);
+      q.y.alloc(m);
+      poff += (int64_t)(2 * m + 3) * ((q.n + kChunk - 1) / kChunk);
     }
-    bt->partial.alloc(poff);
+    int64_t nmax = 0;
+    for (auto& q : bt->sys) nmax = std::max(nmax, q.n);
+    bt->partial.alloc(std::max<int64_t>(poff, multidot_blocks(nmax)));
     bt->hout.alloc((size_t)ns * (2 * m + 3));
     bt->coef.alloc((size_t)ns * (2 * m + 5));
-    bt->ydev.alloc(kMaxM);
+    bt->scal.alloc((size_t)2 * ns);
     bt->dsys.alloc(ns);
-    bt->dcin.alloc(ns);
-    bt->dcout.alloc(ns);
-    if (!bt->hpin) {
-      hchk(hipHostMalloc((void**)&bt->hpin, sizeof(double) * (size_t)ns * (4 * kMaxM + 8)), "pinned");
+    bt->dprm.alloc(1);
+    if (!bt->hsys) {
       hchk(hipHostMalloc((void**)&bt->hsys, sizeof(KrySys) * ns), "pinned");
-      hchk(hipHostMalloc((void**)&bt->hcin, sizeof(CopyDesc) * ns), "pinned");
-      hchk(hipHostMalloc((void**)&bt->hcout, sizeof(CopyDesc) * ns), "pinned");
-      hchk(hipHostMalloc((void**)&bt->hmask, sizeof(int) * ns), "pinned");
+      hchk(hipHostMalloc((void**)&bt->hsnap, sizeof(KrySys) * ns * kRing), "pinned");
+      hchk(hipHostMalloc((void**)&bt->hprm, sizeof(KryParams)), "pinned");
+      hchk(hipHostMalloc((void**)&bt->hscal, sizeof(double) * 2 * ns), "pinned");
+      for (int i = 0; i < kRing; ++i) hchk(hipEventCreateWithFlags(&bt->ev[i], hipEventDisableTiming), "event");
     }
-    // initial residuals (eager, per system): bnorm over free DoFs, r = b - A x0, u = r / beta
-    auto norm2 = [&](const double* v, int64_t n) {
-      hchk(launch_multidot(n, 1, v, n, v, bt->partial.p, multidot_blocks(n), s), "norm");
-      hchk(launch_reduce_partials(1, multidot_blocks(n), bt->partial.p, bt->hout.p, 0, s), "norm");
-      hchk(hipMemcpyAsync(bt->hpin, bt->hout.p, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
-      hchk(hipStreamSynchronize(s), "sync");
-      return bt->hpin[0];
+    // ||r||^2 of a system's r into scal[slot] (device), no host round trip
+    auto norm2_dev = [&](const Sys& q, int slot) {
+      const int nb = multidot_blocks(q.n);
+      hchk(launch_multidot(q.n, 1, q.r.p, q.n, q.r.p, bt->partial.p, nb, s), "norm");
+      hchk(launch_reduce_partials(1, nb, bt->partial.p, bt->scal.p + slot, 0, s), "norm");
     };
     auto residual = [&](Sys& q, const double* xx) {
       Group& g = bt->groups[q.group];
       hchk(launch_apply2d<double, double>(g.k, q.N, c0ip_internal_coef<double>(g.proto, q.L), xx, q.b, q.r.p, s),
            "residual");
     };
-    auto restart = [&](Sys& q) {
-      hchk(launch_multidot(q.n, 1, q.r.p, q.n, q.r.p, bt->partial.p, multidot_blocks(q.n), s), "norm");
-      hchk(launch_reduce_partials(1, multidot_blocks(q.n), bt->partial.p, bt->hout.p, 0, s), "norm");
-      hchk(launch_normalize(q.n, q.r.p, bt->hout.p, q.u.p, s), "normalize");
-      std::fill(q.H.begin(), q.H.end(), 0.0);
-      q.j = 0;
-      q.g0 = q.beta;
-    };
-    for (auto& q : bt->sys) {
+    // initial state: ||b|| over the free DoFs (r = b - A 0) and beta = ||b - A x0||, one host sync for all
+    for (int i = 0; i < ns; ++i) {
+      Sys& q = bt->sys[i];
       hchk(launch_fill(q.n, 0.0, q.u.p, s), "fill");
-      residual(q, q.u.p);  // b with boundary entries ignored
-      q.bnorm = std::sqrt(norm2(q.r.p, q.n));
+      residual(q, q.u.p);
+      norm2_dev(q, 2 * i);
       if (opts->x0_is_zero) hchk(launch_fill(q.n, 0.0, q.x, s), "fill");
       else residual(q, q.x);
-      q.beta = std::sqrt(norm2(q.r.p, q.n));
-      q.its = 0;
-      q.converged = q.bnorm == 0.0 || q.beta <= opts->rtol * q.bnorm;
-      q.active = !q.converged;
-      q.failed = !std::isfinite(q.bnorm) || !std::isfinite(q.beta);
-      if (q.failed) q.active = false;
-      q.last = q.beta;
-      if (q.active) restart(q);
+      norm2_dev(q, 2 * i + 1);
+      hchk(launch_fill((size_t)(m + 1) * m, 0.0, q.H.p, s), "fill");
     }
-    // descriptors that do not change between rounds
-    int64_t off = 0;
+    hchk(hipMemcpyAsync(bt->hscal, bt->scal.p, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost, s), "D2H");
+    hchk(hipStreamSynchronize(s), "sync");
+    int running = 0;
+    std::vector<int> host_epoch(ns, 0), done(ns, 0);
     for (int i = 0; i < ns; ++i) {
       Sys& q = bt->sys[i];
       Group& g = bt->groups[q.group];
-      const int nblk = (int)((q.n + kChunk - 1) / kChunk);
       const int first = (q.L + 1 <= g.Lmax) ? g.A[q.L + 1] : 0;
+      q.bnorm = std::sqrt(bt->hscal[2 * i]);
+      const double beta = std::sqrt(bt->hscal[2 * i + 1]);
       KrySys& d = bt->hsys[i];
+      d = KrySys{};
       d.V = q.V.p;
       d.u = q.u.p;
       d.w = g.W[q.L]->p + (int64_t)(q.slot - first) * q.n;
-      d.n = q.n;
-      d.poff = off;
-      d.nblk = nblk;
-      d.pad = 0;
-      off += (int64_t)(2 * m + 3) * nblk;
-      CopyDesc& ci = bt->hcin[i];
-      ci.src = q.u.p;
-      ci.dst = f32 ? (void*)(g.b32[q.L]->p + (int64_t)q.slot * q.n) : (void*)(g.b64[q.L]->p + (int64_t)q.slot * q.n);
-      ci.n = q.n;
-      ci.mode = f32 ? 1 : 0;
-      CopyDesc& co = bt->hcout[i];
-      co.src = f32 ? (const void*)(g.x32[q.L]->p + (int64_t)q.slot * q.n)
+      d.Z = f32 ? (void*)q.Z32.p : (void*)q.Z64.p;
+      d.vin = f32 ? (void*)(g.b32[q.L]->p + (int64_t)q.slot * q.n) : (void*)(g.b64[q.L]->p + (int64_t)q.slot * q.n);
+      d.vout = f32 ? (const void*)(g.x32[q.L]->p + (int64_t)q.slot * q.n)
                    : (const void*)(g.x64[q.L]->p + (int64_t)q.slot * q.n);
-      co.n = q.n;
-      co.mode = f32 ? 2 : 0;
-    }
-    // capture one round (graph reused while m is unchanged)
-    if (!bt->exec || bt->graph_m != m) {
-      if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
-      if (bt->graph) (void)hipGraphDestroy(bt->graph);
-      bt->exec = nullptr;
-      bt->graph = nullptr;
-      hchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "capture");
-      try {
-        bt->record_round();
-      } catch (...) {
-        hipGraph_t tmp;
-        (void)hipStreamEndCapture(s, &tmp);
-        if (tmp) (void)hipGraphDestroy(tmp);
-        throw;
+      d.mask = g.mask.p + q.slot;
+      d.H = q.H.p;
+      d.y = q.y.p;
+      d.n = q.n;
+      d.nblk = (int)((q.n + kChunk - 1) / kChunk);
+      d.bnorm = q.bnorm;
+      d.beta = d.g0 = d.last = beta;
+      const bool failed = !std::isfinite(q.bnorm) || !std::isfinite(beta);
+      const bool conv = !failed && (q.bnorm == 0.0 || beta <= opts->rtol * q.bnorm);
+      d.status = failed ? kFailed : (conv ? kConverged : kRun);
+      d.active = d.status == kRun ? 1 : 0;
+      if (d.active) {
+        hchk(launch_normalize(q.n, q.r.p, bt->scal.p + 2 * i + 1, q.u.p, s), "normalize");
+        ++running;
+      } else {
+        done[i] = 1;
       }
-      hchk(hipStreamEndCapture(s, &bt->graph), "capture");
-      hchk(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0), "instantiate");
+    }
+    {
+      int64_t off = 0;
+      for (int i = 0; i < ns; ++i) {
+        bt->hsys[i].poff = off;
+        off += (int64_t)(2 * m + 3) * bt->hsys[i].nblk;
+      }
+    }
+    for (auto& g : bt->groups) {  // group masks from the initial state
+      std::vector<int> msk(g.members.size());
+      for (size_t si = 0; si < g.members.size(); ++si) msk[si] = bt->hsys[g.members[si]].active;
+      hchk(hipMemcpy(g.mask.p, msk.data(), sizeof(int) * msk.size(), hipMemcpyHostToDevice), "H2D");
+    }
+    bt->hprm->rtol = opts->rtol;
+    bt->hprm->max_iters = opts->max_iters;
+    hchk(hipMemcpyAsync(bt->dprm.p, bt->hprm, sizeof(KryParams), hipMemcpyHostToDevice, s), "H2D");
+    hchk(hipMemcpyAsync(bt->dsys.p, bt->hsys, sizeof(KrySys) * ns, hipMemcpyHostToDevice, s), "H2D");
+    // capture the round graphs (reused while m is unchanged); they differ in their snapshot slot
+    if (bt->graph_m != m) {
+      for (int i = 0; i < kRing; ++i) {
+        if (bt->exec[i]) (void)hipGraphExecDestroy(bt->exec[i]);
+        if (bt->graph[i]) (void)hipGraphDestroy(bt->graph[i]);
+        bt->exec[i] = nullptr;
+        bt->graph[i] = nullptr;
+      }
+      bt->graph_m = -1;
+      for (int i = 0; i < kRing; ++i) {
+        hchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "capture");
+        try {
+          bt->record_round(i);
+        } catch (...) {
+          hipGraph_t tmp = nullptr;
+          (void)hipStreamEndCapture(s, &tmp);
+          if (tmp) (void)hipGraphDestroy(tmp);
+          throw;
+        }
+        hchk(hipStreamEndCapture(s, &bt->graph[i]), "capture");
+        hchk(hipGraphInstantiate(&bt->exec[i], bt->graph[i], nullptr, nullptr, 0), "instantiate");
+      }
       bt->graph_m = m;
     }
-    std::vector<double> R, gg, y(m);
-    for (;;) {
-      int nact = 0;
+    // Rounds run back to back with no host work between them: the device
+    // advances and stops systems, and the host reads each round's state
+    // snapshot kInFlight rounds later.  A stopped system's x += Z y,
+    // residual and restart (or final beta) are queued behind the rounds in
+    // flight; it sits idle (masked) until they run.  Every active system
+    // spends at least one of its max_iters iterations per kInFlight + 1
+    // rounds, which bounds the number of rounds.
+    const int64_t max_rounds = (int64_t)(kInFlight + 2) * opts->max_iters + 16;
+    int64_t t = 0;
+    while (running > 0) {
+      if (t >= max_rounds) throw HErr{hipErrorUnknown, "batched solve did not finish (internal error)"};
+      const int slot = (int)(t % kRing);
+      hchk(hipGraphLaunch(bt->exec[slot], s), "graph launch");
+      hchk(hipEventRecord(bt->ev[slot], s), "event");
+      ++t;
+      if (t < kInFlight) continue;
+      const int ps = (int)((t - kInFlight) % kRing);
+      hchk(hipEventSynchronize(bt->ev[ps]), "sync");
+      const KrySys* snap = bt->hsnap + (size_t)ps * ns;
       for (int i = 0; i < ns; ++i) {
+        const KrySys& d = snap[i];
+        if (done[i] || d.status == kRun || d.epoch != host_epoch[i]) continue;
         Sys& q = bt->sys[i];
-        KrySys& d = bt->hsys[i];
-        d.j = q.j;
-        d.active = q.active ? 1 : 0;
-        bt->hcin[i].active = d.active;
-        bt->hcout[i].active = d.active;
-        bt->hcout[i].dst = f32 ? (void*)(q.Z32.p + (size_t)q.j * q.n) : (void*)(q.Z64.p + (size_t)q.j * q.n);
-        nact += d.active;
-      }
-      if (nact == 0) break;
-      hchk(hipMemcpyAsync(bt->dsys.p, bt->hsys, sizeof(KrySys) * ns, hipMemcpyHostToDevice, s), "H2D");
-      hchk(hipMemcpyAsync(bt->dcin.p, bt->hcin, sizeof(CopyDesc) * ns, hipMemcpyHostToDevice, s), "H2D");
-      hchk(hipMemcpyAsync(bt->dcout.p, bt->hcout, sizeof(CopyDesc) * ns, hipMemcpyHostToDevice, s), "H2D");
-      {
-        int off = 0;
-        for (auto& g : bt->groups) {
-          for (size_t si = 0; si < g.members.size(); ++si)
-            bt->hmask[off + si] = bt->sys[g.members[si]].active ? 1 : 0;
-          hchk(hipMemcpyAsync(g.mask.p, bt->hmask + off, sizeof(int) * g.members.size(), hipMemcpyHostToDevice, s),
-               "H2D");
-          off += (int)g.members.size();
-        }
-      }
-      hchk(hipGraphLaunch(bt->exec, s), "graph launch");
-      hchk(hipStreamSynchronize(s), "sync");
-      const double* hh = bt->hpin;
-      const double* cc = bt->hpin + (size_t)ns * (2 * m + 3);
-      for (int i = 0; i < ns; ++i) {
-        Sys& q = bt->sys[i];
-        if (!q.active) continue;
-        const int j = q.j;
-        const double* d = hh + (size_t)i * (2 * m + 3);
-        const double* cf = cc + (size_t)i * (2 * m + 5);
-        const double alpha = cf[2 * j + 2], hv = cf[2 * j + 3];
-        if (!std::isfinite(alpha) || !std::isfinite(hv) || !std::isfinite(d[2 * j + 2])) {
-          q.failed = true;
-          q.active = false;
+        if (d.status == kFailed || d.status == kExact) {
+          done[i] = 1;
+          --running;
           continue;
         }
-        if (j == 0) {
-          q.g0 = q.beta * alpha;
-        } else {
-          for (int t = 0; t < j; ++t) q.H[(size_t)t * m + (j - 1)] += d[t];
-          q.H[(size_t)j * m + (j - 1)] = alpha;
-        }
-        double c2 = 0;
-        for (int t = 0; t < j; ++t) {
-          q.H[(size_t)t * m + j] = d[j + t];
-          c2 += d[j + t] * d[j + t];
-        }
-        q.H[(size_t)j * m + j] = hv;
-        const double ww = d[2 * j + 2];
-        double est2 = ww - c2 - hv * hv;
-        if (!(est2 > 1e-10 * ww)) est2 = norm2(q.u.p, q.n);
-        q.H[(size_t)(j + 1) * m + j] = std::sqrt(std::max(est2, 0.0));
-        const double res = lsq(q.H, m, j, q.g0, R, gg);
-        q.its++;
-        q.last = res;
-        const bool conv = res <= opts->rtol * q.bnorm || q.H[(size_t)(j + 1) * m + j] == 0.0;
-        if (conv || j + 1 == m || q.its >= opts->max_iters) {
-          // x += Z y, new residual; restart or stop
-          const int jd = j + 1;
-          lsq(q.H, m, j, q.g0, R, gg);
-          for (int t = jd - 1; t >= 0; --t) {
-            double v = gg[t];
-            for (int l2 = t + 1; l2 < jd; ++l2) v -= R[(size_t)t * jd + l2] * y[l2];
-            y[t] = v / R[(size_t)t * jd + t];
-          }
-          hchk(hipMemcpyAsync(bt->ydev.p, y.data(), jd * sizeof(double), hipMemcpyHostToDevice, s), "H2D");
-          if (f32)
-            hchk(launch_update_solution<float>(q.n, jd, q.Z32.p, q.n, bt->ydev.p, q.x, s), "update x");
-          else
-            hchk(launch_update_solution<double>(q.n, jd, q.Z64.p, q.n, bt->ydev.p, q.x, s), "update x");
-          residual(q, q.x);
-          q.beta = std::sqrt(norm2(q.r.p, q.n));
-          if (conv) {
-            q.converged = true;
-            q.active = false;
-          } else if (q.its >= opts->max_iters) {
-            q.active = false;
-          } else {
-            restart(q);
-          }
-        } else {
-          q.j = j + 1;
+        const int jd = d.j + 1;
+        if (f32)
+          hchk(launch_update_solution<float>(q.n, jd, q.Z32.p, q.n, q.y.p, q.x, s), "update x");
+        else
+          hchk(launch_update_solution<double>(q.n, jd, q.Z64.p, q.n, q.y.p, q.x, s), "update x");
+        residual(q, q.x);
+        norm2_dev(q, 2 * i + 1);
+        if (d.status == kRestart) hchk(launch_normalize(q.n, q.r.p, bt->scal.p + 2 * i + 1, q.u.p, s), "normalize");
+        brestart_kernel<<<1, kThreads, 0, s>>>(bt->dsys.p + i, m, bt->scal.p + 2 * i + 1);
+        hchk(hipGetLastError(), "restart");
+        host_epoch[i]++;
+        if (d.status != kRestart) {
+          done[i] = 1;
+          --running;
         }
       }
     }
+    hchk(hipMemcpyAsync(bt->hsys, bt->dsys.p, sizeof(KrySys) * ns, hipMemcpyDeviceToHost, s), "D2H");
     hchk(hipStreamSynchronize(s), "sync");
-    (void)hipEventDestroy(ev);
     auto t1 = std::chrono::steady_clock::now();
     const double secs = std::chrono::duration<double>(t1 - t0).count();
     bool all = true, anynan = false;
     for (int i = 0; i < ns; ++i) {
-      Sys& q = bt->sys[i];
-      all = all && q.converged;
-      anynan = anynan || q.failed || !std::isfinite(q.beta);
+      const KrySys& d = bt->hsys[i];
+      const double bn = bt->sys[i].bnorm;
+      const bool conv = d.status == kConverged || d.status == kExact;
+      all = all && conv;
+      anynan = anynan || d.status == kFailed || !std::isfinite(d.beta);
       if (infos) {
         c0ip_solve_info& inf = infos[i];
         inf = c0ip_solve_info{};
-        inf.iterations = q.its;
-        inf.converged = q.converged ? 1 : 0;
-        inf.rel_res_est = q.bnorm > 0 ? q.last / q.bnorm : 0.0;
-        inf.rel_res_true = q.bnorm > 0 ? q.beta / q.bnorm : 0.0;
-        inf.frac_iters =
-            (q.its > 0 && inf.rel_res_est > 0) ? 8.0 * q.its / (-std::log10(inf.rel_res_est)) : 0.0;
+        inf.iterations = d.its;
+        inf.converged = conv ? 1 : 0;
+        inf.rel_res_est = bn > 0 ? d.last / bn : 0.0;
+        inf.rel_res_true = bn > 0 ? d.beta / bn : 0.0;
+        inf.frac_iters = (d.its > 0 && inf.rel_res_est > 0) ? 8.0 * d.its / (-std::log10(inf.rel_res_est)) : 0.0;
         inf.seconds_total = secs;
       }
     }
@@ -894,6 +1009,7 @@ c0ip_status c0ip_batch_solve(c0ip_batch* bt, const c0ip_krylov_opts* opts, const
     (void)hipStreamSynchronize(s);
     result = bfail(C0IP_EHIP, std::string(h.what) + ": " + hipGetErrorString(h.e));
   }
+  if (ev) (void)hipEventDestroy(ev);
   return result;
 }
 

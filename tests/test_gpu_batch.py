@@ -1,7 +1,8 @@
-"""Batched solves (many uneven 2D systems, one captured graph per round)
-against the eager single-system solve of each system: equal iteration
-counts and solutions, over two consecutive batched solves (every round is
-a graph replay; restarts and finalisations run eagerly in between)."""
+"""Batched solves (many uneven 2D systems, one captured graph per round,
+the Krylov state and Givens steps on the device) against the eager
+single-system solve of each system: equal iteration counts and solutions,
+over two consecutive batched solves (rounds are graph replays queued back
+to back; solution updates and restarts are queued between them)."""
 import numpy as np
 import pytest
 import torch
@@ -89,6 +90,35 @@ def test_batch_restart_and_max_iters():
     xs = [torch.zeros_like(b) for b in bs]
     infos = bt.solve(bs, xs, rtol=1e-8, restart=50, max_iters=2, raise_on_nonconv=False)
     assert all(inf["iterations"] == 2 and inf["converged"] == 0 for inf in infos)
+
+
+def test_batch_zero_rhs_and_initial_guess():
+    """A zero right-hand side stops before the first round (0 iterations,
+    x untouched); a warm-started system (x0 from a loose solve) takes the
+    single solve's iterations and solution; a system that converges in the
+    first rounds goes idle while the others run on."""
+    say("batch zero rhs / initial guess")
+    probs, nrhs = [(16, 3), (32, 2)], [2, 1]
+    b0 = torch.from_numpy(_rhs(16, 3, 2, 40)).cuda()
+    b0[1].zero_()
+    b1 = torch.from_numpy(_rhs(32, 2, 1, 41)).cuda()
+    pb1 = P.Problem(2, 32, 2, omega=0.25)
+    xw = torch.zeros_like(b1[0])
+    pb1.solve(b1[0].contiguous(), xw, rtol=1e-3)
+    xs = [torch.zeros_like(b0), xw.clone().reshape(1, -1).contiguous()]
+    bt = P.Batch(probs, nrhs, omega=0.25)
+    infos = bt.solve([b0, b1], xs, rtol=1e-8, x0_is_zero=False)
+    assert infos[1]["iterations"] == 0 and infos[1]["converged"] == 1
+    assert float(xs[0][1].abs().max()) == 0.0
+    pb0 = P.Problem(2, 16, 3, omega=0.25)
+    xr = torch.zeros_like(b0[0])
+    info = pb0.solve(b0[0].contiguous(), xr, rtol=1e-8)
+    assert infos[0]["iterations"] == info["iterations"]
+    assert np.linalg.norm(host(xs[0][0]) - host(xr)) <= 1e-10 * np.linalg.norm(host(xr))
+    xr1 = xw.clone()
+    info1 = pb1.solve(b1[0].contiguous(), xr1, rtol=1e-8, x0_is_zero=False)
+    assert infos[2]["iterations"] == info1["iterations"] and infos[2]["converged"] == 1
+    assert np.linalg.norm(host(xs[1][0]) - host(xr1)) <= 1e-10 * np.linalg.norm(host(xr1))
 
 
 def test_batch_rejects_3d_and_bad_shapes():
