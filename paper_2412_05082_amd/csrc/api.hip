@@ -104,7 +104,9 @@ struct c0ip_problem {
   std::vector<double> ptab;  // prolongation table (float64 host copy)
   DevBuf<double> A0inv;
   // Krylov work space
-  DevBuf<double> V, w, u, partial, hdev, coef, ydev, r64;
+  DevBuf<double> V, w, u, partial, hdev, ydev, r64;  // hdev: dots, then coefficients
+  DevBuf<unsigned> arn_counter;                      // last-block counter of the reduction
+  hipStream_t copy_stream = nullptr;                 // the per-step copy to the host
   DevBuf<double> Z64;
   DevBuf<float> Z32;
   // flexible CG work space
@@ -139,6 +141,7 @@ struct c0ip_problem {
   ~c0ip_problem() {
     invalidate_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (copy_stream) (void)hipStreamDestroy(copy_stream);
     if (hpin) (void)hipHostFree(hpin);
   }
 
@@ -1042,7 +1045,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   auto t0 = std::chrono::steady_clock::now();
   double t_vc = 0;
   c0ip_status result = C0IP_OK;
-  hipEvent_t e0 = nullptr, e1 = nullptr, ef = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr, ef = nullptr, ed = nullptr;
   int its = 0;
   double last_est = 0, bnorm_out = 0;
   try {
@@ -1053,8 +1056,13 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     p->r64.alloc(n);
     p->u.alloc(n);
     p->partial.alloc((size_t)(2 * m + 3) * nblk);
-    p->hdev.alloc(2 * m + 3);
-    p->coef.alloc(2 * m + 5);
+    p->hdev.alloc(4 * m + 8);  // [0, 2m+3): dots; [2m+3, 4m+8): coefficients (one copy to the host)
+    if (!p->arn_counter.p) {
+      p->arn_counter.alloc(1);
+      p->check(hipMemset(p->arn_counter.p, 0, sizeof(unsigned)), "memset");
+    }
+    if (!p->copy_stream) p->check(hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking), "stream");
+    double* coefd = p->hdev.p + 2 * m + 3;
     p->ydev.alloc(m);
     if (!p->hpin) p->check(hipHostMalloc((void**)&p->hpin, sizeof(double) * (4 * 64 + 16)), "pinned alloc");
     if (f32) {
@@ -1068,6 +1076,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     p->check(hipEventCreate(&e0), "event");
     p->check(hipEventCreate(&e1), "event");
     p->check(hipEventCreateWithFlags(&ef, hipEventDisableTiming), "event");
+    p->check(hipEventCreateWithFlags(&ed, hipEventDisableTiming), "event");
     double* hh = p->hpin;  // [0, 2m+3): dots; [2m+3, 4m+8): coefficients
     auto norm2 = [&](const double* v) {
       p->check(c0ip::launch_multidot(n, 1, v, n, v, p->partial.p, nblk, s), "multidot");
@@ -1126,14 +1135,17 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
         (void)zf32;
         // one reduction: V^T u, V^T w, u.u, u.w, w.w; coefficients on the device
         p->check(c0ip::launch_arnoldi_dots(n, j, p->V.p, n, p->u.p, p->w.p, p->partial.p, nblk_a, s), "dots");
-        p->check(c0ip::launch_reduce_partials(2 * j + 3, nblk_a, p->partial.p, p->hdev.p, 0, s), "reduce");
-        p->check(c0ip::launch_arnoldi_coef(j, p->hdev.p, p->coef.p, s), "coef");
-        p->check(hipMemcpyAsync(hh, p->hdev.p, (2 * j + 3) * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
-        p->check(hipMemcpyAsync(hh + 2 * m + 3, p->coef.p, (2 * j + 5) * sizeof(double), hipMemcpyDeviceToHost, s),
+        p->check(c0ip::launch_arnoldi_reduce_coef(j, nblk_a, p->partial.p, p->hdev.p, coefd, p->arn_counter.p, s),
+                 "reduce");
+        // dots and coefficients to the host on the copy stream, beside the update
+        p->check(hipEventRecord(ed, s), "event");
+        p->check(hipStreamWaitEvent(p->copy_stream, ed, 0), "wait");
+        p->check(hipMemcpyAsync(hh, p->hdev.p, (2 * m + 3 + 2 * j + 5) * sizeof(double), hipMemcpyDeviceToHost,
+                                p->copy_stream),
                  "D2H");
-        p->check(hipEventRecord(ef, s), "event");
+        p->check(hipEventRecord(ef, p->copy_stream), "event");
         // V_j = (u - V s)/alpha ; u <- w - V c - V_j h_v   (overlaps the host work below)
-        p->check(c0ip::launch_arnoldi_update(n, j, p->V.p, n, p->u.p, p->w.p, p->coef.p, p->V.p + (size_t)j * n, s),
+        p->check(c0ip::launch_arnoldi_update(n, j, p->V.p, n, p->u.p, p->w.p, coefd, p->V.p + (size_t)j * n, s),
                  "update");
         p->check(hipEventSynchronize(ef), "sync");
         float ms = 0;
@@ -1203,6 +1215,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (ef) (void)hipEventDestroy(ef);
+  if (ed) (void)hipEventDestroy(ed);
   auto t1 = std::chrono::steady_clock::now();
   inf.seconds_total = std::chrono::duration<double>(t1 - t0).count();
   inf.seconds_vcycle = t_vc;

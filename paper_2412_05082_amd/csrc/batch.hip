@@ -74,6 +74,9 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
+// NT: non-temporal loads of the bases (when together they exceed the
+// last-level cache).
+template <bool NT>
 __global__ __launch_bounds__(kThreads) void bdots_kernel(const KrySys* __restrict__ sys, double* __restrict__ partial) {
   const KrySys d = sys[blockIdx.y];
   if (!d.active || (int)blockIdx.x >= d.nblk) return;
@@ -116,7 +119,8 @@ __global__ __launch_bounds__(kThreads) void bdots_kernel(const KrySys* __restric
 #pragma unroll
         for (int e = 0; e < kPer; ++e) {
           const int64_t i = base + (int64_t)e * kThreads;
-          const double v = i < d.n ? vq[i] : 0.0;
+          double v = 0.0;
+          if (i < d.n) v = NT ? __builtin_nontemporal_load(vq + i) : vq[i];
           au[q] += v * ur[e];
           aw[q] += v * wr[e];
         }
@@ -637,7 +641,12 @@ void c0ip_batch::record_round(int slot) {
              "A z");
     }
   }
-  bdots_kernel<<<dim3(maxblk, ns), kThreads, 0, s>>>(dsys.p, partial.p);
+  double vbytes = 0;
+  for (auto& q : sys) vbytes += (double)q.n * m * sizeof(double);
+  if (vbytes > 256.0 * (1 << 20))
+    bdots_kernel<true><<<dim3(maxblk, ns), kThreads, 0, s>>>(dsys.p, partial.p);
+  else
+    bdots_kernel<false><<<dim3(maxblk, ns), kThreads, 0, s>>>(dsys.p, partial.p);
   hchk(hipGetLastError(), "dots");
   breduce_kernel<<<dim3(2 * m + 3, ns), kThreads, 0, s>>>(dsys.p, m, partial.p, hout.p);
   hchk(hipGetLastError(), "reduce");

@@ -79,12 +79,15 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_
 int multidot_blocks(int64_t n);
 
 // Arnoldi step with delayed re-orthogonalisation (see kernels_common.hip).
-// dots: partial[(2j+3) * nblk]; coef: one thread, writes 2j+5 values;
+// dots: partial[(2j+3) * nblk]; reduce_coef: d[2j+3] and coef[2j+5];
 // update: V_j = (u - V s)/alpha into vout, u <- w - V f - (h_v/alpha) u.
 int arnoldi_blocks(int64_t n);
 hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, const double* u, const double* w,
                                double* partial, int nblk, hipStream_t s);
-hipError_t launch_arnoldi_coef(int j, const double* d, double* coef, hipStream_t s);
+// d[row] = sum of partial row (2j+3 rows), then coef from d (2j+5 values);
+// counter: one device word, zero before the first launch (left zero).
+hipError_t launch_arnoldi_reduce_coef(int j, int nblk, const double* partial, double* d, double* coef,
+                                      unsigned* counter, hipStream_t s);
 hipError_t launch_arnoldi_update(int64_t n, int j, const double* V, int64_t ldv, double* u, const double* w,
                                  const double* coef, double* vout, hipStream_t s);
 

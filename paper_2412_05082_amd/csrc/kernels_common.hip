@@ -347,6 +347,9 @@ constexpr int kArnPer = 8;
 constexpr int kArnChunk = kThreads * kArnPer;
 constexpr int kArnVec = 4;
 
+// NT: the basis is read with non-temporal loads (taken when it is larger
+// than the last-level cache, which it would only flush).
+template <bool NT>
 __global__ __launch_bounds__(kThreads) void arnoldi_dots_kernel(int64_t n, int j, const double* __restrict__ V,
                                                                 int64_t ldv, const double* __restrict__ u,
                                                                 const double* __restrict__ w,
@@ -391,7 +394,8 @@ __global__ __launch_bounds__(kThreads) void arnoldi_dots_kernel(int64_t n, int j
 #pragma unroll
         for (int e = 0; e < kArnPer; ++e) {
           const int64_t i = base + (int64_t)e * kThreads;
-          const double v = i < n ? vq[i] : 0.0;
+          double v = 0.0;
+          if (i < n) v = NT ? __builtin_nontemporal_load(vq + i) : vq[i];
           au[q] += v * ur[e];
           aw[q] += v * wr[e];
         }
@@ -422,8 +426,7 @@ __global__ __launch_bounds__(kThreads) void arnoldi_dots_kernel(int64_t n, int j
 // One thread: coefficients of the update from the reduced dots d[0..2j+2].
 // coef layout: [0, j): e_i = s_i / alpha ; [j, 2j): f_i = c_i - s_i h_v / alpha ;
 // 2j: 1/alpha ; 2j+1: h_v/alpha ; 2j+2: alpha ; 2j+3: h_v ; 2j+4: |s|^2/u.u
-__global__ void arnoldi_coef_kernel(int j, const double* __restrict__ d, double* __restrict__ coef) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void arnoldi_coef(int j, const double* __restrict__ d, double* __restrict__ coef) {
   double ss = 0, sc = 0;
   for (int i = 0; i < j; ++i) {
     ss += d[i] * d[i];
@@ -443,6 +446,39 @@ __global__ void arnoldi_coef_kernel(int j, const double* __restrict__ d, double*
   coef[2 * j + 2] = alpha;
   coef[2 * j + 3] = hv;
   coef[2 * j + 4] = uu > 0 ? ss / uu : 0.0;
+}
+
+// Row sums of the dots' partials (one block per row, d[row], as
+// reduce_partials_kernel), then the coefficients, computed by the block that
+// finishes last: it learns so from a counter that it resets for the next
+// launch.  Every block publishes its row with a device-scope release before
+// counting, and the last one acquires before reading d.
+__global__ __launch_bounds__(kThreads) void arnoldi_reduce_coef_kernel(int j, int nblk,
+                                                                       const double* __restrict__ partial,
+                                                                       double* __restrict__ d,
+                                                                       double* __restrict__ coef,
+                                                                       unsigned* __restrict__ counter) {
+  __shared__ double red[kThreads / 64];
+  __shared__ unsigned last;
+  const int row = blockIdx.x;
+  double s = 0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) s += partial[(int64_t)row * nblk + b];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int q = 0; q < kThreads / 64; ++q) t += red[q];
+    d[row] = t;
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    arnoldi_coef(j, d, coef);
+    atomicExch(counter, 0u);
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void arnoldi_update_kernel(int64_t n, int j, const double* __restrict__ V,
@@ -580,12 +616,19 @@ int arnoldi_blocks(int64_t n) { return (int)((n + kArnChunk - 1) / kArnChunk); }
 hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, const double* u, const double* w,
                                double* partial, int nblk, hipStream_t s) {
   if ((int64_t)nblk * kArnChunk < n) return hipErrorInvalidValue;
-  arnoldi_dots_kernel<<<nblk, kThreads, 0, s>>>(n, j, V, ldv, u, w, partial, nblk);
+  // measured on a 2.36 M-entry basis: non-temporal loads are 10 % faster
+  // once the basis exceeds the 256 MiB last-level cache, slower below
+  if ((double)j * (double)n * sizeof(double) > 256.0 * (1 << 20))
+    arnoldi_dots_kernel<true><<<nblk, kThreads, 0, s>>>(n, j, V, ldv, u, w, partial, nblk);
+  else
+    arnoldi_dots_kernel<false><<<nblk, kThreads, 0, s>>>(n, j, V, ldv, u, w, partial, nblk);
   return hipGetLastError();
 }
 
-hipError_t launch_arnoldi_coef(int j, const double* d, double* coef, hipStream_t s) {
-  arnoldi_coef_kernel<<<1, 64, 0, s>>>(j, d, coef);
+hipError_t launch_arnoldi_reduce_coef(int j, int nblk, const double* partial, double* d, double* coef,
+                                      unsigned* counter, hipStream_t s) {
+  if (j < 0 || j > kMaxDot) return hipErrorInvalidValue;
+  arnoldi_reduce_coef_kernel<<<2 * j + 3, kThreads, 0, s>>>(j, nblk, partial, d, coef, counter);
   return hipGetLastError();
 }
 
