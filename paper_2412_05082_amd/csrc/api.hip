@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -106,7 +107,7 @@ struct c0ip_problem {
   // Krylov work space
   DevBuf<double> V, w, u, partial, hdev, ydev, r64;  // hdev: dots, then coefficients
   DevBuf<unsigned> arn_counter;                      // last-block counter of the reduction
-  hipStream_t copy_stream = nullptr;                 // the per-step copy to the host
+  double arn_seq = 0;                                // tag of the last Arnoldi reduction
   DevBuf<double> Z64;
   DevBuf<float> Z32;
   // flexible CG work space
@@ -141,7 +142,6 @@ struct c0ip_problem {
   ~c0ip_problem() {
     invalidate_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    if (copy_stream) (void)hipStreamDestroy(copy_stream);
     if (hpin) (void)hipHostFree(hpin);
   }
 
@@ -470,12 +470,33 @@ void c0ip_problem::mg_level(int l, const T* b, T* x) {
   }
 }
 
-// z = MG_L(0, u) in precision T (u float64; the float32 form casts it into
-// the finest level's b first), as one replay of a captured graph.  Every
+// z = MG_L(0, u) in precision T, launched eagerly or as one replay of a
+// captured graph.  u is float64; in the float32 form u == NULL means that the
+// input is already in the finest level's float32 b (else it is cast there
+// first).  Every
 // launch of the V-cycle goes to the handle's stream and allocates nothing
 // once the levels are prepared, so the captured sequence is the eager one.
 template <typename T>
 void c0ip_problem::vcycle_graph(const double* u, T* z) {
+  // Eager launches by default: with the host polling the Arnoldi reduction
+  // it runs ahead of the device and the launches queue back to back, while a
+  // graph replay leaves the device idle for ~8 us at its end (measured).
+  // C0IP_VCYCLE_GRAPH=1 selects the captured graph.
+  static const bool graph = [] {
+    const char* e = std::getenv("C0IP_VCYCLE_GRAPH");
+    return e && e[0] == '1';
+  }();
+  if (!graph) {
+    for (int l = 0; l <= L; ++l) prepare<T>(l);
+    if constexpr (sizeof(T) == 4) {
+      LevelWork<float>& wf = work<float>(L);
+      if (u) check(c0ip::launch_cast<double, float>(ntot(L), u, wf.b.p, stream), "cast");
+      mg_level<float>(L, wf.b.p, (float*)z);
+    } else {
+      mg_level<double>(L, u, (double*)z);
+    }
+    return;
+  }
   VGraph& g = vgraph[sizeof(T) == 4 ? 1 : 0];
   if (!g.exec || g.in != u || g.out != z) {
     g.release();
@@ -489,7 +510,7 @@ void c0ip_problem::vcycle_graph(const double* u, T* z) {
     try {
       if constexpr (sizeof(T) == 4) {
         LevelWork<float>& wf = work<float>(L);
-        check(c0ip::launch_cast<double, float>(ntot(L), u, wf.b.p, stream), "cast");
+        if (u) check(c0ip::launch_cast<double, float>(ntot(L), u, wf.b.p, stream), "cast");
         mg_level<float>(L, wf.b.p, (float*)z);
       } else {
         mg_level<double>(L, u, (double*)z);
@@ -1004,6 +1025,10 @@ c0ip_status c0ip_vcycle(c0ip_problem* p, c0ip_dtype dtype, const void* b, void* 
   return C0IP_OK;
 }
 
+// The Krylov solves time their V-cycles with an event pair on every
+// kTimeEvery-th iteration and scale the sum to all iterations.
+constexpr int kTimeEvery = 8;
+
 // Givens QR of the (j+2) x (j+1) Hessenberg H (row-major, leading dim m)
 // applied to g0 e_1; returns |g_{j+1}| and leaves R, g for back substitution.
 static double hessenberg_lsq(const std::vector<double>& H, int m, int j, double g0, std::vector<double>& R,
@@ -1044,8 +1069,9 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   c0ip_solve_info inf{};
   auto t0 = std::chrono::steady_clock::now();
   double t_vc = 0;
+  int n_timed = 0;
   c0ip_status result = C0IP_OK;
-  hipEvent_t e0 = nullptr, e1 = nullptr, ef = nullptr, ed = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   int its = 0;
   double last_est = 0, bnorm_out = 0;
   try {
@@ -1061,10 +1087,10 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
       p->arn_counter.alloc(1);
       p->check(hipMemset(p->arn_counter.p, 0, sizeof(unsigned)), "memset");
     }
-    if (!p->copy_stream) p->check(hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking), "stream");
     double* coefd = p->hdev.p + 2 * m + 3;
     p->ydev.alloc(m);
-    if (!p->hpin) p->check(hipHostMalloc((void**)&p->hpin, sizeof(double) * (4 * 64 + 16)), "pinned alloc");
+    if (!p->hpin)
+      p->check(hipHostMalloc((void**)&p->hpin, sizeof(double) * (4 * 64 + 16), hipHostMallocCoherent), "pinned alloc");
     if (f32) {
       p->Z32.alloc((size_t)m * n);
       p->zfix32.alloc(n);
@@ -1075,9 +1101,9 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     }
     p->check(hipEventCreate(&e0), "event");
     p->check(hipEventCreate(&e1), "event");
-    p->check(hipEventCreateWithFlags(&ef, hipEventDisableTiming), "event");
-    p->check(hipEventCreateWithFlags(&ed, hipEventDisableTiming), "event");
     double* hh = p->hpin;  // [0, 2m+3): dots; [2m+3, 4m+8): coefficients
+    double* hh_dev = nullptr;  // the same memory as the kernels address it
+    p->check(hipHostGetDevicePointer((void**)&hh_dev, hh, 0), "host pointer");
     auto norm2 = [&](const double* v) {
       p->check(c0ip::launch_multidot(n, 1, v, n, v, p->partial.p, nblk, s), "multidot");
       p->check(c0ip::launch_reduce_partials(1, nblk, p->partial.p, p->hdev.p, 0, s), "reduce");
@@ -1113,44 +1139,74 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
       int jdone = 0;
       bool stop = false;
       for (int j = 0; j < m && !stop; ++j) {
-        p->check(hipEventRecord(e0, s), "event");
+        // V-cycle time sampled on every kTimeEvery-th iteration (an event
+        // pair in the stream idles the GPU for a few microseconds)
+        const bool timed = its % kTimeEvery == 0;
+        if (timed) p->check(hipEventRecord(e0, s), "event");
         const double* Zp;
         bool zf32 = f32;
+        // z = M u into Z_j; in 2D the operator's launch A z writes that copy
         if (f32) {
           float* Zj = p->Z32.p + (size_t)j * n;
-          p->vcycle_graph<float>(p->u.p, p->zfix32.p);
-          p->check(hipEventRecord(e1, s), "event");
-          p->check(hipMemcpyAsync(Zj, p->zfix32.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s), "copy z");
-          p->check(c0ip::launch_apply<float, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
+          float* u32 = p->work<float>(Lf).b.p;  // the previous update wrote (float) u there
+          if (j == 0) p->check(c0ip::launch_cast<double, float>(n, p->u.p, u32, s), "cast");
+          p->vcycle_graph<float>(nullptr, p->zfix32.p);
+          if (timed) p->check(hipEventRecord(e1, s), "event");
+          if (p->dim == 2) {
+            p->check(c0ip::launch_apply2d<float, double>(p->k, p->N, cf64, p->zfix32.p, nullptr, p->w.p, s, 1, 0,
+                                                         nullptr, Zj),
+                     "A z");
+          } else {
+            p->check(hipMemcpyAsync(Zj, p->zfix32.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s), "copy z");
+            p->check(c0ip::launch_apply<float, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
+          }
           Zp = nullptr;
         } else {
           double* Zj = p->Z64.p + (size_t)j * n;
           p->vcycle_graph<double>(p->u.p, p->zfix64.p);
-          p->check(hipEventRecord(e1, s), "event");
-          p->check(hipMemcpyAsync(Zj, p->zfix64.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy z");
-          p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
+          if (timed) p->check(hipEventRecord(e1, s), "event");
+          if (p->dim == 2) {
+            p->check(c0ip::launch_apply2d<double, double>(p->k, p->N, cf64, p->zfix64.p, nullptr, p->w.p, s, 1, 0,
+                                                          nullptr, Zj),
+                     "A z");
+          } else {
+            p->check(hipMemcpyAsync(Zj, p->zfix64.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy z");
+            p->check(c0ip::launch_apply<double, double>(p->dim, p->k, p->N, cf64, Zj, nullptr, p->w.p, s), "A z");
+          }
           Zp = Zj;
         }
         (void)Zp;
         (void)zf32;
         // one reduction: V^T u, V^T w, u.u, u.w, w.w; coefficients on the device
         p->check(c0ip::launch_arnoldi_dots(n, j, p->V.p, n, p->u.p, p->w.p, p->partial.p, nblk_a, s), "dots");
-        p->check(c0ip::launch_arnoldi_reduce_coef(j, nblk_a, p->partial.p, p->hdev.p, coefd, p->arn_counter.p, s),
+        // sums and coefficients, also written straight into the pinned host
+        // buffer, followed by this step's tag, which the host polls for
+        const double tag = (double)(++p->arn_seq);
+        volatile double* htag = hh + 4 * m + 8;
+        p->check(c0ip::launch_arnoldi_reduce_coef(j, nblk_a, p->partial.p, p->hdev.p, coefd, p->arn_counter.p, hh_dev,
+                                                  2 * m + 3, 4 * m + 8, tag, s),
                  "reduce");
-        // dots and coefficients to the host on the copy stream, beside the update
-        p->check(hipEventRecord(ed, s), "event");
-        p->check(hipStreamWaitEvent(p->copy_stream, ed, 0), "wait");
-        p->check(hipMemcpyAsync(hh, p->hdev.p, (2 * m + 3 + 2 * j + 5) * sizeof(double), hipMemcpyDeviceToHost,
-                                p->copy_stream),
-                 "D2H");
-        p->check(hipEventRecord(ef, p->copy_stream), "event");
         // V_j = (u - V s)/alpha ; u <- w - V c - V_j h_v   (overlaps the host work below)
-        p->check(c0ip::launch_arnoldi_update(n, j, p->V.p, n, p->u.p, p->w.p, coefd, p->V.p + (size_t)j * n, s),
+        p->check(c0ip::launch_arnoldi_update(n, j, p->V.p, n, p->u.p, p->w.p, coefd, p->V.p + (size_t)j * n, s,
+                                             f32 ? p->work<float>(Lf).b.p : nullptr),
                  "update");
-        p->check(hipEventSynchronize(ef), "sync");
-        float ms = 0;
-        p->check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-        t_vc += ms * 1e-3;
+        {
+          // spin on the tag; after 10 s (a failed launch) wait for the stream and look once more
+          const auto tw = std::chrono::steady_clock::now();
+          while (*htag != tag) {
+            if (std::chrono::steady_clock::now() - tw > std::chrono::seconds(10)) {
+              p->check(hipStreamSynchronize(s), "sync");
+              if (*htag != tag) throw HipFail{hipErrorUnknown, "Arnoldi reduction did not complete"};
+            }
+          }
+        }
+        if (timed) {
+          float ms = 0;
+          p->check(hipEventSynchronize(e1), "sync");
+          p->check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+          t_vc += ms * 1e-3;
+          ++n_timed;
+        }
         const double* d = hh;
         const double* cf = hh + 2 * m + 3;
         const double alpha = cf[2 * j + 2], hv = cf[2 * j + 3];
@@ -1214,11 +1270,9 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  if (ef) (void)hipEventDestroy(ef);
-  if (ed) (void)hipEventDestroy(ed);
   auto t1 = std::chrono::steady_clock::now();
   inf.seconds_total = std::chrono::duration<double>(t1 - t0).count();
-  inf.seconds_vcycle = t_vc;
+  inf.seconds_vcycle = n_timed > 0 ? t_vc * its / n_timed : 0.0;
   inf.seconds_arnoldi = std::max(0.0, inf.seconds_total - t_vc);
   if (info) *info = inf;
   return result;
@@ -1254,7 +1308,8 @@ c0ip_status c0ip_solve_fcg(c0ip_problem* p, const c0ip_krylov_opts* opts, const 
     } else {
       p->cg_z64.alloc(n);
     }
-    if (!p->hpin) p->check(hipHostMalloc((void**)&p->hpin, sizeof(double) * (4 * 64 + 16)), "pinned alloc");
+    if (!p->hpin)
+      p->check(hipHostMalloc((void**)&p->hpin, sizeof(double) * (4 * 64 + 16), hipHostMallocCoherent), "pinned alloc");
     p->check(hipEventCreate(&e0), "event");
     p->check(hipEventCreate(&e1), "event");
     double* hh = p->hpin;
@@ -1285,7 +1340,10 @@ c0ip_status c0ip_solve_fcg(c0ip_problem* p, const c0ip_krylov_opts* opts, const 
       if (!std::isfinite(rr)) throw c0ip_status(C0IP_ENAN);
       const int first = its == 0;
       p->check(hipEventRecord(e0, s), "event");
-      if (f32) p->vcycle_graph<float>(r, p->cg_z32.p);
+      if (f32) {
+        p->check(c0ip::launch_cast<double, float>(n, r, p->work<float>(Lf).b.p, s), "cast");
+        p->vcycle_graph<float>(nullptr, p->cg_z32.p);
+      }
       else p->vcycle_graph<double>(r, p->cg_z64.p);
       p->check(hipEventRecord(e1, s), "event");
       // beta = (z . q_old) / (p_old . q_old); p = z - beta p_old

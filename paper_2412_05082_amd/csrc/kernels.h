@@ -85,18 +85,25 @@ int arnoldi_blocks(int64_t n);
 hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, const double* u, const double* w,
                                double* partial, int nblk, hipStream_t s);
 // d[row] = sum of partial row (2j+3 rows), then coef from d (2j+5 values);
-// counter: one device word, zero before the first launch (left zero).
+// counter: one device word, zero before the first launch (left zero);
+// host: NULL or device-visible pinned memory that receives d at [0, 2j+3)
+// and coef at [hoff, hoff + 2j+5), then (tagpos >= 0) host[tagpos] = tag,
+// written after the data, so the host may poll for it.
 hipError_t launch_arnoldi_reduce_coef(int j, int nblk, const double* partial, double* d, double* coef,
-                                      unsigned* counter, hipStream_t s);
+                                      unsigned* counter, double* host, int hoff, int tagpos, double tag,
+                                      hipStream_t s);
+// u32: NULL, or receives (float) of the new u (the next float32 V-cycle's input).
 hipError_t launch_arnoldi_update(int64_t n, int j, const double* V, int64_t ldv, double* u, const double* w,
-                                 const double* coef, double* vout, hipStream_t s);
+                                 const double* coef, double* vout, hipStream_t s, float* u32 = nullptr);
 
 // Per-dimension operator and smoother launchers (k dispatched at run time).
 // Batched forms (2D): nsys systems whose vectors are zs elements apart
 // (fine / coarse strides zf / zc for the transfers); nsys = 1 for one.
+// xc: NULL, or (one system) receives a copy of x, written from the staged
+// tiles (saves a separate copy where x is needed again).
 template <typename Tin, typename T>
 hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s,
-                          int nsys = 1, int64_t zs = 0, const int* active = nullptr);
+                          int nsys = 1, int64_t zs = 0, const int* active = nullptr, Tin* xc = nullptr);
 template <typename T>
 hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const T* xin, T* xout, T omega,
                           hipStream_t s, int nsys = 1, int64_t zs = 0, const int* active = nullptr);

@@ -452,13 +452,18 @@ __device__ void arnoldi_coef(int j, const double* __restrict__ d, double* __rest
 // reduce_partials_kernel), then the coefficients, computed by the block that
 // finishes last: it learns so from a counter that it resets for the next
 // launch.  Every block publishes its row with a device-scope release before
-// counting, and the last one acquires before reading d.
+// counting, and the last one acquires before reading d.  The last block also
+// writes the sums and coefficients to host memory (host[0, 2j+3) and
+// host[hoff, hoff+2j+5)) when host is not NULL, so that no copy follows.
 __global__ __launch_bounds__(kThreads) void arnoldi_reduce_coef_kernel(int j, int nblk,
                                                                        const double* __restrict__ partial,
                                                                        double* __restrict__ d,
                                                                        double* __restrict__ coef,
-                                                                       unsigned* __restrict__ counter) {
+                                                                       unsigned* __restrict__ counter,
+                                                                       double* __restrict__ host, int hoff,
+                                                                       int tagpos, double tag) {
   __shared__ double red[kThreads / 64];
+  __shared__ double sd[2 * kMaxDot + 3], sc[2 * kMaxDot + 5];
   __shared__ unsigned last;
   const int row = blockIdx.x;
   double s = 0;
@@ -474,10 +479,26 @@ __global__ __launch_bounds__(kThreads) void arnoldi_reduce_coef_kernel(int j, in
     last = atomicAdd(counter, 1u) == gridDim.x - 1 ? 1u : 0u;
   }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    arnoldi_coef(j, d, coef);
+  if (!last) return;
+  __threadfence();
+  const int nd = 2 * j + 3, nc = 2 * j + 5;
+  for (int i = threadIdx.x; i < nd; i += kThreads) sd[i] = d[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    arnoldi_coef(j, sd, sc);
     atomicExch(counter, 0u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nc; i += kThreads) coef[i] = sc[i];
+  if (host) {
+    for (int i = threadIdx.x; i < nd; i += kThreads) host[i] = sd[i];
+    for (int i = threadIdx.x; i < nc; i += kThreads) host[hoff + i] = sc[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0 && tagpos >= 0) {  // after the data: the host may poll for it
+      host[tagpos] = tag;
+      __threadfence_system();
+    }
   }
 }
 
@@ -485,7 +506,8 @@ __global__ __launch_bounds__(kThreads) void arnoldi_update_kernel(int64_t n, int
                                                                   int64_t ldv, double* __restrict__ u,
                                                                   const double* __restrict__ w,
                                                                   const double* __restrict__ coef,
-                                                                  double* __restrict__ vout) {
+                                                                  double* __restrict__ vout,
+                                                                  float* __restrict__ u32) {
   __shared__ double se[kMaxDot], sf[kMaxDot];
   for (int t = threadIdx.x; t < kMaxDot; t += kThreads) {
     se[t] = t < j ? coef[t] : 0.0;
@@ -513,7 +535,9 @@ __global__ __launch_bounds__(kThreads) void arnoldi_update_kernel(int64_t n, int
       sw += sf[q] * v;
     }
     vout[i] = ui * inv - sv;
-    u[i] = wi - sw - d * ui;
+    const double un = wi - sw - d * ui;
+    u[i] = un;
+    if (u32) u32[i] = (float)un;
   }
 }
 
@@ -626,15 +650,17 @@ hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, c
 }
 
 hipError_t launch_arnoldi_reduce_coef(int j, int nblk, const double* partial, double* d, double* coef,
-                                      unsigned* counter, hipStream_t s) {
+                                      unsigned* counter, double* host, int hoff, int tagpos, double tag,
+                                      hipStream_t s) {
   if (j < 0 || j > kMaxDot) return hipErrorInvalidValue;
-  arnoldi_reduce_coef_kernel<<<2 * j + 3, kThreads, 0, s>>>(j, nblk, partial, d, coef, counter);
+  arnoldi_reduce_coef_kernel<<<2 * j + 3, kThreads, 0, s>>>(j, nblk, partial, d, coef, counter, host, hoff,
+                                                            tagpos, tag);
   return hipGetLastError();
 }
 
 hipError_t launch_arnoldi_update(int64_t n, int j, const double* V, int64_t ldv, double* u, const double* w,
-                                 const double* coef, double* vout, hipStream_t s) {
-  arnoldi_update_kernel<<<grid_for(n), kThreads, 0, s>>>(n, j, V, ldv, u, w, coef, vout);
+                                 const double* coef, double* vout, hipStream_t s, float* u32) {
+  arnoldi_update_kernel<<<grid_for(n), kThreads, 0, s>>>(n, j, V, ldv, u, w, coef, vout, u32);
   return hipGetLastError();
 }
 

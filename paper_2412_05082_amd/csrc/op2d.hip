@@ -15,10 +15,12 @@ int avs2d_variants(int k) {
   }
 }
 template hipError_t launch_apply2d<double, double>(int, int, const LevelCoef<double>&, const double*,
-                                                   const double*, double*, hipStream_t, int, int64_t, const int*);
+                                                   const double*, double*, hipStream_t, int, int64_t, const int*,
+                                                   double*);
 template hipError_t launch_apply2d<float, double>(int, int, const LevelCoef<double>&, const float*,
-                                                  const double*, double*, hipStream_t, int, int64_t, const int*);
+                                                  const double*, double*, hipStream_t, int, int64_t, const int*,
+                                                  float*);
 template hipError_t launch_apply2d<float, float>(int, int, const LevelCoef<float>&, const float*, const float*,
-                                                 float*, hipStream_t, int, int64_t, const int*);
+                                                 float*, hipStream_t, int, int64_t, const int*, float*);
 
 }  // namespace c0ip

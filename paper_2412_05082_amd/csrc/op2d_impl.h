@@ -208,7 +208,8 @@ template <typename Tin, typename T, class G, bool RES>
 __global__ __launch_bounds__(G::NTH) void apply2d_kernel(const Tin* __restrict__ x, const T* __restrict__ b,
                                                          T* __restrict__ y, int n1, const T* __restrict__ tab,
                                                          int nclass, int left, int right0, int periodic, int64_t zs,
-                                                         const int* __restrict__ active, tile::TileOrder ord) {
+                                                         const int* __restrict__ active, tile::TileOrder ord,
+                                                         Tin* __restrict__ xc) {
   if (active && !active[blockIdx.z]) return;
   int bx, by;
   if (!tile::tile_of_block(ord, blockIdx.x, bx, by)) return;
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(G::NTH) void apply2d_kernel(const Tin* __restrict__
       const int gy = y0 + cg * G::RW * G::K + w;
       if (gx < n1 && gy < n1) {
         const size_t idx = (size_t)gy * n1 + gx;
+        if (xc) xc[idx] = (Tin)sX[(cg * G::RW * G::K + w + G::H) * G::RX + l + G::H];  // exact: T holds every Tin
         if constexpr (RES) {
           const bool bnd = gx == 0 || gy == 0 || gx == n1 - 1 || gy == n1 - 1;
           y[idx] = bnd ? T(0) : bv[q][w] - acc[q][w];
@@ -286,7 +288,8 @@ template <> struct ApplyCfgSmall<7> { using G = Geo<7, 2, 2, 64, 2, 2>; };
 
 template <typename Tin, typename T, class G>
 hipError_t apply2d_g(int n1, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s, int nsys,
-                     int64_t zs, const int* active) {
+                     int64_t zs, const int* active, Tin* xc) {
+  if (xc && nsys != 1) return hipErrorInvalidValue;
   const int tx = (n1 + G::TX - 1) / G::TX, ty = (n1 + G::TY - 1) / G::TY;
   const tile::TileOrder ord = tile::make_order(
       tx, ty, [&](int bx) { return c.periodic && bx * G::TX >= c.left && bx * G::TX + G::TX <= c.right0; },
@@ -294,21 +297,21 @@ hipError_t apply2d_g(int n1, const LevelCoef<T>& c, const Tin* x, const T* b, T*
   const dim3 grid(tile::order_blocks(ord), 1, nsys);
   if (b)
     apply2d_kernel<Tin, T, G, true><<<grid, G::NTH, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left, c.right0,
-                                                            c.periodic, zs, active, ord);
+                                                            c.periodic, zs, active, ord, xc);
   else
     apply2d_kernel<Tin, T, G, false><<<grid, G::NTH, 0, s>>>(x, b, y, n1, c.tab, c.nclass, c.left, c.right0,
-                                                             c.periodic, zs, active, ord);
+                                                             c.periodic, zs, active, ord, xc);
   return hipGetLastError();
 }
 
 template <typename Tin, typename T, int K>
 hipError_t apply2d_k(int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s, int nsys,
-                     int64_t zs, const int* active) {
+                     int64_t zs, const int* active, Tin* xc) {
   using G = typename ApplyCfg<K>::G;
   const int n1 = K * N + 1;
   const int64_t big = (int64_t)((n1 + G::TX - 1) / G::TX) * ((n1 + G::TY - 1) / G::TY) * nsys;
-  if (big < 256) return apply2d_g<Tin, T, typename ApplyCfgSmall<K>::G>(n1, c, x, b, y, s, nsys, zs, active);
-  return apply2d_g<Tin, T, G>(n1, c, x, b, y, s, nsys, zs, active);
+  if (big < 256) return apply2d_g<Tin, T, typename ApplyCfgSmall<K>::G>(n1, c, x, b, y, s, nsys, zs, active, xc);
+  return apply2d_g<Tin, T, G>(n1, c, x, b, y, s, nsys, zs, active, xc);
 }
 
 // ------------------------------------------------------------------ smoother
@@ -788,8 +791,8 @@ hipError_t avs2d_k(int N, const LevelCoef<T>& c, const LevelEig<T>& e, const T* 
 
 template <typename Tin, typename T>
 hipError_t launch_apply2d(int k, int N, const LevelCoef<T>& c, const Tin* x, const T* b, T* y, hipStream_t s,
-                          int nsys, int64_t zs, const int* active) {
-#define CALL(K) apply2d_k<Tin, T, K>(N, c, x, b, y, s, nsys, zs, active)
+                          int nsys, int64_t zs, const int* active, Tin* xc) {
+#define CALL(K) apply2d_k<Tin, T, K>(N, c, x, b, y, s, nsys, zs, active, xc)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
