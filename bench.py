@@ -83,6 +83,11 @@ def measured_traffic(variant):
     return None
 
 
+def progress(msg):
+    """One progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def only_kernel(args):
     """One kernel's timing loop on the bench workload, nothing else: used to
     collect hardware counters for it (and, with copy_f64, for a plain device
@@ -547,6 +552,7 @@ def main():
     pat.close()
     del sets32
     torch.cuda.empty_cache()
+    progress(f"C2 kernel loops done (S(x,b) f32 {1e3 * ms_smx32:.1f} us)")
 
     # --- solves: all-float64 V-cycle vs float32 V-cycle (timed steps use the latter)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -570,6 +576,7 @@ def main():
     tsteps = time.perf_counter() - t0
     ms_step = 1e3 * tsteps / args.steps
     value = n * args.steps / tsteps
+    progress(f"C2 solves done (mixed {ms_step:.2f} ms, float64 {1e3 * t64:.2f} ms)")
 
     # dominant kernel of the float32 V-cycle: the fused smoother step S(x, b)
     bytes_sm32 = 12.0 * n  # read x, read b, write x_out (float32)
@@ -625,18 +632,24 @@ def main():
     }
     if not args.no_extra:
         out.update(bench_extra(args, torch, P, b, x_np))
+        progress("extra C2 legs done")
     if not args.no_batch:
         out["config_batched"] = bench_batch(torch, P)
+        progress("batched workload done")
     if not args.no_sweep:
         out["config_degree_sweep"] = bench_sweep(args, torch, P)
+        progress("degree sweep done")
     if not args.no_3d:
         del pmix, p64
         torch.cuda.empty_cache()
         out["config_3d_q3_128"] = bench_3d(args, torch, P)
+        progress("3D Q3 128^3 done")
     if not args.no_3d_sweep:
         out["config_3d_mixed_sweep"] = bench_3d_sweep(args, torch, P)
+        progress("3D sweep done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(k, args.cpu_N, args.omega)
+        progress("CPU baseline done")
     print(json.dumps(out), flush=True)
 
 

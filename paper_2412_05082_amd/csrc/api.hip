@@ -106,8 +106,6 @@ struct c0ip_problem {
   DevBuf<double> A0inv;
   // Krylov work space
   DevBuf<double> V, w, u, partial, hdev, ydev, r64;  // hdev: dots, then coefficients
-  DevBuf<unsigned> arn_counter;                      // last-block counter of the reduction
-  double arn_seq = 0;                                // tag of the last Arnoldi reduction
   DevBuf<double> Z64;
   DevBuf<float> Z32;
   // flexible CG work space
@@ -1071,7 +1069,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   double t_vc = 0;
   int n_timed = 0;
   c0ip_status result = C0IP_OK;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr, ef = nullptr;
   int its = 0;
   double last_est = 0, bnorm_out = 0;
   try {
@@ -1083,10 +1081,6 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     p->u.alloc(n);
     p->partial.alloc((size_t)(2 * m + 3) * nblk);
     p->hdev.alloc(4 * m + 8);  // [0, 2m+3): dots; [2m+3, 4m+8): coefficients (one copy to the host)
-    if (!p->arn_counter.p) {
-      p->arn_counter.alloc(1);
-      p->check(hipMemset(p->arn_counter.p, 0, sizeof(unsigned)), "memset");
-    }
     double* coefd = p->hdev.p + 2 * m + 3;
     p->ydev.alloc(m);
     if (!p->hpin)
@@ -1101,6 +1095,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
     }
     p->check(hipEventCreate(&e0), "event");
     p->check(hipEventCreate(&e1), "event");
+    p->check(hipEventCreateWithFlags(&ef, hipEventDisableTiming), "event");
     double* hh = p->hpin;  // [0, 2m+3): dots; [2m+3, 4m+8): coefficients
     double* hh_dev = nullptr;  // the same memory as the kernels address it
     p->check(hipHostGetDevicePointer((void**)&hh_dev, hh, 0), "host pointer");
@@ -1180,26 +1175,18 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
         // one reduction: V^T u, V^T w, u.u, u.w, w.w; coefficients on the device
         p->check(c0ip::launch_arnoldi_dots(n, j, p->V.p, n, p->u.p, p->w.p, p->partial.p, nblk_a, s), "dots");
         // sums and coefficients, also written straight into the pinned host
-        // buffer, followed by this step's tag, which the host polls for
-        const double tag = (double)(++p->arn_seq);
-        volatile double* htag = hh + 4 * m + 8;
-        p->check(c0ip::launch_arnoldi_reduce_coef(j, nblk_a, p->partial.p, p->hdev.p, coefd, p->arn_counter.p, hh_dev,
-                                                  2 * m + 3, 4 * m + 8, tag, s),
+        // buffer; the event marks the end of that launch
+        p->check(c0ip::launch_arnoldi_reduce_coef(j, nblk_a, p->partial.p, p->hdev.p, coefd, hh_dev, 2 * m + 3, s),
                  "reduce");
+        p->check(hipEventRecord(ef, s), "event");
         // V_j = (u - V s)/alpha ; u <- w - V c - V_j h_v   (overlaps the host work below)
         p->check(c0ip::launch_arnoldi_update(n, j, p->V.p, n, p->u.p, p->w.p, coefd, p->V.p + (size_t)j * n, s,
                                              f32 ? p->work<float>(Lf).b.p : nullptr),
                  "update");
-        {
-          // spin on the tag; after 10 s (a failed launch) wait for the stream and look once more
-          const auto tw = std::chrono::steady_clock::now();
-          while (*htag != tag) {
-            if (std::chrono::steady_clock::now() - tw > std::chrono::seconds(10)) {
-              p->check(hipStreamSynchronize(s), "sync");
-              if (*htag != tag) throw HipFail{hipErrorUnknown, "Arnoldi reduction did not complete"};
-            }
-          }
-        }
+        // the host reads the sums once the reduction has completed (the
+        // update runs meanwhile); stores of a kernel to pinned memory are
+        // ordered for the host only by the launch's completion
+        p->check(hipEventSynchronize(ef), "sync");
         if (timed) {
           float ms = 0;
           p->check(hipEventSynchronize(e1), "sync");
@@ -1270,6 +1257,7 @@ c0ip_status c0ip_solve(c0ip_problem* p, const c0ip_krylov_opts* opts, const doub
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  if (ef) (void)hipEventDestroy(ef);
   auto t1 = std::chrono::steady_clock::now();
   inf.seconds_total = std::chrono::duration<double>(t1 - t0).count();
   inf.seconds_vcycle = n_timed > 0 ? t_vc * its / n_timed : 0.0;

@@ -85,13 +85,10 @@ int arnoldi_blocks(int64_t n);
 hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, const double* u, const double* w,
                                double* partial, int nblk, hipStream_t s);
 // d[row] = sum of partial row (2j+3 rows), then coef from d (2j+5 values);
-// counter: one device word, zero before the first launch (left zero);
 // host: NULL or device-visible pinned memory that receives d at [0, 2j+3)
-// and coef at [hoff, hoff + 2j+5), then (tagpos >= 0) host[tagpos] = tag,
-// written after the data, so the host may poll for it.
+// and coef at [hoff, hoff + 2j+5), readable once the launches have completed.
 hipError_t launch_arnoldi_reduce_coef(int j, int nblk, const double* partial, double* d, double* coef,
-                                      unsigned* counter, double* host, int hoff, int tagpos, double tag,
-                                      hipStream_t s);
+                                      double* host, int hoff, hipStream_t s);
 // u32: NULL, or receives (float) of the new u (the next float32 V-cycle's input).
 hipError_t launch_arnoldi_update(int64_t n, int j, const double* V, int64_t ldv, double* u, const double* w,
                                  const double* coef, double* vout, hipStream_t s, float* u32 = nullptr);

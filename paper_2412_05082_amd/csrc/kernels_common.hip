@@ -448,57 +448,24 @@ __device__ void arnoldi_coef(int j, const double* __restrict__ d, double* __rest
   coef[2 * j + 4] = uu > 0 ? ss / uu : 0.0;
 }
 
-// Row sums of the dots' partials (one block per row, d[row], as
-// reduce_partials_kernel), then the coefficients, computed by the block that
-// finishes last: it learns so from a counter that it resets for the next
-// launch.  Every block publishes its row with a device-scope release before
-// counting, and the last one acquires before reading d.  The last block also
-// writes the sums and coefficients to host memory (host[0, 2j+3) and
-// host[hoff, hoff+2j+5)) when host is not NULL, so that no copy follows.
-__global__ __launch_bounds__(kThreads) void arnoldi_reduce_coef_kernel(int j, int nblk,
-                                                                       const double* __restrict__ partial,
-                                                                       double* __restrict__ d,
-                                                                       double* __restrict__ coef,
-                                                                       unsigned* __restrict__ counter,
-                                                                       double* __restrict__ host, int hoff,
-                                                                       int tagpos, double tag) {
-  __shared__ double red[kThreads / 64];
+// One block: the update coefficients from the reduced sums d (written by the
+// previous launch) into coef and, when host is not NULL, the sums and the
+// coefficients into host memory (host[0, 2j+3) and host[hoff, hoff+2j+5)),
+// so that no copy follows; the host reads them once the launch has
+// completed (an event).
+__global__ __launch_bounds__(kThreads) void arnoldi_coef_kernel(int j, const double* __restrict__ d,
+                                                                double* __restrict__ coef,
+                                                                double* __restrict__ host, int hoff) {
   __shared__ double sd[2 * kMaxDot + 3], sc[2 * kMaxDot + 5];
-  __shared__ unsigned last;
-  const int row = blockIdx.x;
-  double s = 0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) s += partial[(int64_t)row * nblk + b];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0;
-    for (int q = 0; q < kThreads / 64; ++q) t += red[q];
-    d[row] = t;
-    __threadfence();
-    last = atomicAdd(counter, 1u) == gridDim.x - 1 ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
   const int nd = 2 * j + 3, nc = 2 * j + 5;
   for (int i = threadIdx.x; i < nd; i += kThreads) sd[i] = d[i];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    arnoldi_coef(j, sd, sc);
-    atomicExch(counter, 0u);
-  }
+  if (threadIdx.x == 0) arnoldi_coef(j, sd, sc);
   __syncthreads();
   for (int i = threadIdx.x; i < nc; i += kThreads) coef[i] = sc[i];
   if (host) {
     for (int i = threadIdx.x; i < nd; i += kThreads) host[i] = sd[i];
     for (int i = threadIdx.x; i < nc; i += kThreads) host[hoff + i] = sc[i];
-    __threadfence_system();
-    __syncthreads();
-    if (threadIdx.x == 0 && tagpos >= 0) {  // after the data: the host may poll for it
-      host[tagpos] = tag;
-      __threadfence_system();
-    }
   }
 }
 
@@ -650,11 +617,10 @@ hipError_t launch_arnoldi_dots(int64_t n, int j, const double* V, int64_t ldv, c
 }
 
 hipError_t launch_arnoldi_reduce_coef(int j, int nblk, const double* partial, double* d, double* coef,
-                                      unsigned* counter, double* host, int hoff, int tagpos, double tag,
-                                      hipStream_t s) {
+                                      double* host, int hoff, hipStream_t s) {
   if (j < 0 || j > kMaxDot) return hipErrorInvalidValue;
-  arnoldi_reduce_coef_kernel<<<2 * j + 3, kThreads, 0, s>>>(j, nblk, partial, d, coef, counter, host, hoff,
-                                                            tagpos, tag);
+  reduce_partials_kernel<<<2 * j + 3, kThreads, 0, s>>>(nblk, partial, d, 0);
+  arnoldi_coef_kernel<<<1, kThreads, 0, s>>>(j, d, coef, host, hoff);
   return hipGetLastError();
 }
 
