@@ -132,7 +132,8 @@ typedef struct {
   double frac_iters;   /* 8 n / (-log10(rel_res_est)) (Sec. 5.1) */
   /* wall time of the solve; time in the V-cycles (c0ip_solve: events on
    * every 8th iteration, scaled to all iterations; c0ip_solve_fcg: every
-   * iteration); the rest */
+   * iteration); the rest (A z, the Krylov vector passes and reductions, the
+   * host's Hessenberg work, restarts) */
   double seconds_total, seconds_vcycle, seconds_arnoldi;
 } c0ip_solve_info;
 
