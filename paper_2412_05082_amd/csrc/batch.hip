@@ -36,6 +36,8 @@ constexpr int kThreads = 256;
 constexpr int kPer = 8;                 // entries per lane in the dot kernel
 constexpr int kChunk = kThreads * kPer;  // entries per dot block
 constexpr int kVec = 4;
+constexpr int kEl = 4;                  // entries per lane in the copy and update kernels
+constexpr int kElBlock = kThreads * kEl;
 constexpr int kMaxM = 64;
 constexpr int kRing = 3;      // round graphs (and state snapshots) in rotation
 constexpr int kInFlight = 2;  // rounds queued ahead of the host's reading of the state
@@ -58,7 +60,8 @@ struct KrySys {
   double* y;         // m coefficients of the update x += Z y
   int64_t n;
   int64_t poff;  // offset of its partial sums
-  int nblk;
+  int nblk;      // its blocks in the dots kernel
+  int d0, u0;    // its first block in the dots grid and in the copy / update grid
   // changed on the device
   int j, its, status, active, epoch;
   double bnorm, beta, g0, last;
@@ -76,13 +79,18 @@ __device__ __forceinline__ double wsum(double v) {
 
 // NT: non-temporal loads of the bases (when together they exceed the
 // last-level cache).
+// Grids of the Krylov kernels hold exactly each system's blocks, back to back:
+// map[block] = its system, and the system's first block (d0 / u0) gives the
+// block's place in it.
 template <bool NT>
-__global__ __launch_bounds__(kThreads) void bdots_kernel(const KrySys* __restrict__ sys, double* __restrict__ partial) {
-  const KrySys d = sys[blockIdx.y];
-  if (!d.active || (int)blockIdx.x >= d.nblk) return;
+__global__ __launch_bounds__(kThreads) void bdots_kernel(const KrySys* __restrict__ sys, const int* __restrict__ map,
+                                                         double* __restrict__ partial) {
+  const KrySys d = sys[map[blockIdx.x]];
+  if (!d.active) return;
+  const int lb = blockIdx.x - d.d0;
   __shared__ double red[kThreads / 64][2 * kVec];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, j = d.j;
-  const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+  const int64_t base = (int64_t)lb * kChunk + threadIdx.x;
   double* P = partial + d.poff;
   double ur[kPer], wr[kPer], e0 = 0, e1 = 0, e2 = 0;
 #pragma unroll
@@ -105,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void bdots_kernel(const KrySys* __restric
     if (threadIdx.x < 3) {
       double s = 0;
       for (int q = 0; q < kThreads / 64; ++q) s += red[q][threadIdx.x];
-      P[(int64_t)(2 * j + threadIdx.x) * d.nblk + blockIdx.x] = s;
+      P[(int64_t)(2 * j + threadIdx.x) * d.nblk + lb] = s;
     }
     __syncthreads();
   }
@@ -140,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void bdots_kernel(const KrySys* __restric
       if (i0 + q < j) {
         double s = 0;
         for (int r = 0; r < kThreads / 64; ++r) s += red[r][t];
-        P[(int64_t)(t < kVec ? i0 + q : j + i0 + q) * d.nblk + blockIdx.x] = s;
+        P[(int64_t)(t < kVec ? i0 + q : j + i0 + q) * d.nblk + lb] = s;
       }
     }
     __syncthreads();
@@ -199,12 +207,13 @@ __global__ void bcoef_kernel(const KrySys* __restrict__ sys, int nsys, int m, co
   c[2 * j + 4] = uu > 0 ? ss / uu : 0.0;
 }
 
-__global__ __launch_bounds__(kThreads) void bupdate_kernel(const KrySys* __restrict__ sys, int m,
-                                                           const double* __restrict__ coef) {
-  const KrySys d = sys[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void bupdate_kernel(const KrySys* __restrict__ sys, const int* __restrict__ map,
+                                                           int m, const double* __restrict__ coef) {
+  const int si = map[blockIdx.x];
+  const KrySys d = sys[si];
   if (!d.active) return;
   const int j = d.j;
-  const double* c = coef + (int64_t)blockIdx.y * (2 * m + 5);
+  const double* c = coef + (int64_t)si * (2 * m + 5);
   __shared__ double se[kMaxM], sf[kMaxM];
   for (int t = threadIdx.x; t < kMaxM; t += kThreads) {
     se[t] = t < j ? c[t] : 0.0;
@@ -213,16 +222,32 @@ __global__ __launch_bounds__(kThreads) void bupdate_kernel(const KrySys* __restr
   __syncthreads();
   const double inv = c[2 * j], dd = c[2 * j + 1];
   double* vout = d.V + (int64_t)j * d.n;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads) {
-    const double ui = d.u[i], wi = d.w[i];
-    double sv = 0, sw = 0;
-    for (int q = 0; q < j; ++q) {
-      const double v = d.V[(int64_t)q * d.n + i];
-      sv += se[q] * v;
-      sw += sf[q] * v;
+  const int64_t base = (int64_t)(blockIdx.x - d.u0) * kElBlock + threadIdx.x;
+  double sv[kEl], sw[kEl];
+#pragma unroll
+  for (int e = 0; e < kEl; ++e) sv[e] = sw[e] = 0.0;
+  for (int q = 0; q < j; ++q) {  // kEl independent loads per basis vector
+    const double* vq = d.V + (int64_t)q * d.n;
+    double v[kEl];
+#pragma unroll
+    for (int e = 0; e < kEl; ++e) {
+      const int64_t i = base + (int64_t)e * kThreads;
+      v[e] = i < d.n ? vq[i] : 0.0;
     }
-    vout[i] = ui * inv - sv;
-    d.u[i] = wi - sw - dd * ui;
+#pragma unroll
+    for (int e = 0; e < kEl; ++e) {
+      sv[e] += se[q] * v[e];
+      sw[e] += sf[q] * v[e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kEl; ++e) {
+    const int64_t i = base + (int64_t)e * kThreads;
+    if (i < d.n) {
+      const double ui = d.u[i], wi = d.w[i];
+      vout[i] = ui * inv - sv[e];
+      d.u[i] = wi - sw[e] - dd * ui;
+    }
   }
 }
 
@@ -367,28 +392,34 @@ __global__ __launch_bounds__(kThreads) void brestart_kernel(KrySys* __restrict__
 }
 
 template <typename Tv>
-__global__ __launch_bounds__(kThreads) void bcopy_in_kernel(const KrySys* __restrict__ sys) {
-  const KrySys d = sys[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void bcopy_in_kernel(const KrySys* __restrict__ sys,
+                                                            const int* __restrict__ map) {
+  const KrySys d = sys[map[blockIdx.x]];
   if (!d.active) return;
   Tv* dst = (Tv*)d.vin;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads)
-    dst[i] = (Tv)d.u[i];
+  const int64_t base = (int64_t)(blockIdx.x - d.u0) * kElBlock + threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kEl; ++e) {
+    const int64_t i = base + (int64_t)e * kThreads;
+    if (i < d.n) dst[i] = (Tv)d.u[i];
+  }
 }
 
 template <typename Tz>
-__global__ __launch_bounds__(kThreads) void bcopy_out_kernel(const KrySys* __restrict__ sys) {
-  const KrySys d = sys[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void bcopy_out_kernel(const KrySys* __restrict__ sys,
+                                                             const int* __restrict__ map) {
+  const KrySys d = sys[map[blockIdx.x]];
   if (!d.active) return;
   const Tz* src = (const Tz*)d.vout;
   Tz* dst = (Tz*)d.Z + (int64_t)d.j * d.n;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads)
-    dst[i] = src[i];
+  const int64_t base = (int64_t)(blockIdx.x - d.u0) * kElBlock + threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kEl; ++e) {
+    const int64_t i = base + (int64_t)e * kThreads;
+    if (i < d.n) dst[i] = src[i];
+  }
 }
 
-int blocks_for(int64_t n) {
-  int64_t b = (n + kThreads - 1) / kThreads;
-  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 4096);
-}
 
 }  // namespace
 }  // namespace c0ip
@@ -451,6 +482,8 @@ struct Group {
   std::vector<std::unique_ptr<Buf<double>>> x64, b64, r64, t64;
   std::vector<std::unique_ptr<Buf<double>>> W;  // A z of systems whose finest level is l
   Buf<int> mask;
+  hipStream_t stream = nullptr;  // its branch of a round (groups after the first)
+  hipEvent_t join_ev = nullptr;
 };
 
 }  // namespace
@@ -466,6 +499,8 @@ struct c0ip_batch {
   int m = 0;
   Buf<KrySys> dsys;
   Buf<KryParams> dprm;
+  Buf<int> umap, dmap;  // block -> system maps of the copy / update and the dots grids
+  int64_t umap_n = 0, dmap_n = 0;
   Buf<double> partial, hout, coef, scal;
   KrySys* hsys = nullptr;  // pinned: the solve's initial state, then the final one
   KrySys* hsnap = nullptr;  // pinned: kRing snapshots of the state, one per round in flight
@@ -474,6 +509,7 @@ struct c0ip_batch {
   hipGraph_t graph[kRing] = {};
   hipGraphExec_t exec[kRing] = {};
   hipEvent_t ev[kRing] = {};
+  hipEvent_t fork_ev = nullptr;
   int graph_m = -1;
   ~c0ip_batch() {
     for (int i = 0; i < kRing; ++i) {
@@ -481,7 +517,12 @@ struct c0ip_batch {
       if (graph[i]) (void)hipGraphDestroy(graph[i]);
       if (ev[i]) (void)hipEventDestroy(ev[i]);
     }
-    for (auto& g : groups) c0ip_destroy(g.proto);
+    for (auto& g : groups) {
+      c0ip_destroy(g.proto);
+      if (g.join_ev) (void)hipEventDestroy(g.join_ev);
+      if (g.stream) (void)hipStreamDestroy(g.stream);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (hsys) (void)hipHostFree(hsys);
     if (hsnap) (void)hipHostFree(hsnap);
     if (hprm) (void)hipHostFree(hprm);
@@ -490,7 +531,8 @@ struct c0ip_batch {
   }
 
   template <typename T>
-  void vcycle(Group& g);
+  void vcycle(Group& g, hipStream_t gs);
+  void az(Group& g, hipStream_t st, bool f32);
   void record_round(int slot);
 };
 
@@ -507,7 +549,7 @@ Buf<double>& lvbuf<double>(Group& g, int which, int l) {
 
 // Algorithm 1 for every system of the group at once (see the file comment).
 template <typename T>
-void c0ip_batch::vcycle(Group& g) {
+void c0ip_batch::vcycle(Group& g, hipStream_t gs) {
   const int k = g.k, pre = mg.pre_steps, post = mg.post_steps;
   const T om = (T)mg.omega;
   auto n1 = [&](int l) { return (int64_t)(k * (2 << l) + 1) * (k * (2 << l) + 1); };
@@ -529,19 +571,19 @@ void c0ip_batch::vcycle(Group& g) {
     T* A = (post % 2 == 1) ? lvbuf<T>(g, 3, l).p : x;
     T* B = (A == x) ? lvbuf<T>(g, 3, l).p : x;
     if (pre == 0) {
-      hchk(launch_fill_t<T>(nA * nl, T(0), A, s), "fill");
+      hchk(launch_fill_t<T>(nA * nl, T(0), A, gs), "fill");
     } else {
       T* cur = (pre % 2 == 1) ? A : B;
-      hchk(launch_patch2d<T>(k, Nl, eig, b, nullptr, cur, om, s, nA, nl, mask), "patch");
+      hchk(launch_patch2d<T>(k, Nl, eig, b, nullptr, cur, om, gs, nA, nl, mask), "patch");
       for (int st = 1; st < pre; ++st) {
         T* nxt = (cur == A) ? B : A;
-        hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, nxt, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
+        hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, nxt, om, gs, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
              "fused smoother");
         cur = nxt;
       }
     }
-    hchk(launch_apply2d<T, T>(k, Nl, coef, A, b, r, s, nA, nl, mask), "residual");
-    hchk(launch_restrict2d<T>(k, Nl / 2, c0ip_internal_ptab<T>(g.proto, l), r, lvbuf<T>(g, 1, l - 1).p, s, nA, nl,
+    hchk(launch_apply2d<T, T>(k, Nl, coef, A, b, r, gs, nA, nl, mask), "residual");
+    hchk(launch_restrict2d<T>(k, Nl / 2, c0ip_internal_ptab<T>(g.proto, l), r, lvbuf<T>(g, 1, l - 1).p, gs, nA, nl,
                               n1(l - 1), mask),
          "restrict");
   }
@@ -554,16 +596,16 @@ void c0ip_batch::vcycle(Group& g) {
       io.nA[l] = g.A[l];
     }
     io.active = mask;
-    hchk(launch_vtail<T>(k, tp, io, g.A[0], s), "tail V-cycle");
+    hchk(launch_vtail<T>(k, tp, io, g.A[0], gs), "tail V-cycle");
   } else {
     const int nA = g.A[0];
     if (mg.coarse_mode == 0)
-      hchk(launch_coarse<T>(2, k, c0ip_internal_coarse(g.proto), lvbuf<T>(g, 1, 0).p, lvbuf<T>(g, 0, 0).p, s, nA,
+      hchk(launch_coarse<T>(2, k, c0ip_internal_coarse(g.proto), lvbuf<T>(g, 1, 0).p, lvbuf<T>(g, 0, 0).p, gs, nA,
                             n1(0), mask),
            "coarse");
     else
       hchk(launch_patch2d<T>(k, 2, c0ip_internal_eig<T>(g.proto, 0), lvbuf<T>(g, 1, 0).p, nullptr,
-                             lvbuf<T>(g, 0, 0).p, T(1), s, nA, n1(0), mask),
+                             lvbuf<T>(g, 0, 0).p, T(1), gs, nA, n1(0), mask),
            "coarse smooth");
   }
   for (int l = lo + 1; l <= g.Lmax; ++l) {
@@ -578,20 +620,39 @@ void c0ip_batch::vcycle(Group& g) {
     T* A = (post % 2 == 1) ? lvbuf<T>(g, 3, l).p : x;
     T* B = (A == x) ? lvbuf<T>(g, 3, l).p : x;
     if (post == 0) {
-      hchk(launch_prolong2d<T>(k, Nl / 2, ptab, lvbuf<T>(g, 0, l - 1).p, A, x, s, nA, n1(l - 1), nl, mask), "prolong");
+      hchk(launch_prolong2d<T>(k, Nl / 2, ptab, lvbuf<T>(g, 0, l - 1).p, A, x, gs, nA, n1(l - 1), nl, mask), "prolong");
       continue;
     }
     // first post-smoothing step from A + P e (fused), then alternate; ends in x
-    hchk(launch_avs2d<T>(k, Nl, coef, eig, A, b, B, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l),
+    hchk(launch_avs2d<T>(k, Nl, coef, eig, A, b, B, om, gs, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l),
                          lvbuf<T>(g, 0, l - 1).p, ptab, n1(l - 1)),
          "prolongation + fused smoother");
     T* cur = B;
     for (int st = 1; st < post; ++st) {
       T* nxt = (cur == A) ? B : A;
-      hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, nxt, om, s, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
+      hchk(launch_avs2d<T>(k, Nl, coef, eig, cur, b, nxt, om, gs, nA, nl, mask, c0ip_internal_variant<T>(g.proto, l)),
            "fused smoother");
       cur = nxt;
     }
+  }
+}
+
+// A z for every system of the group, at each system's finest level, into W.
+void c0ip_batch::az(Group& g, hipStream_t st, bool f32) {
+  for (int l = 1; l <= g.Lmax; ++l) {
+    const int first = (l + 1 <= g.Lmax) ? g.A[l + 1] : 0, cnt = g.A[l] - first;
+    if (cnt <= 0) continue;
+    const int Nl = 2 << l;
+    const int64_t nl = (int64_t)(g.k * Nl + 1) * (g.k * Nl + 1);
+    const auto& c64 = c0ip_internal_coef<double>(g.proto, l);
+    if (f32)
+      hchk(launch_apply2d<float, double>(g.k, Nl, c64, g.x32[l]->p + first * nl, nullptr, g.W[l]->p, st, cnt, nl,
+                                         g.mask.p + first),
+           "A z");
+    else
+      hchk(launch_apply2d<double, double>(g.k, Nl, c64, g.x64[l]->p + first * nl, nullptr, g.W[l]->p, st, cnt, nl,
+                                          g.mask.p + first),
+           "A z");
   }
 }
 
@@ -601,58 +662,47 @@ void c0ip_batch::vcycle(Group& g) {
 void c0ip_batch::record_round(int slot) {
   const int ns = (int)sys.size();
   const bool f32 = mg.vcycle_dtype == C0IP_F32;
-  int64_t nmax = 0;
-  int maxblk = 1;
-  for (auto& q : sys) {
-    nmax = std::max(nmax, q.n);
-    maxblk = std::max(maxblk, (int)((q.n + kChunk - 1) / kChunk));
-  }
-  const dim3 grid(blocks_for(nmax), ns);
+  const int gu = (int)umap_n, gd = (int)dmap_n;
   if (f32)
-    bcopy_in_kernel<float><<<grid, kThreads, 0, s>>>(dsys.p);
+    bcopy_in_kernel<float><<<gu, kThreads, 0, s>>>(dsys.p, umap.p);
   else
-    bcopy_in_kernel<double><<<grid, kThreads, 0, s>>>(dsys.p);
+    bcopy_in_kernel<double><<<gu, kThreads, 0, s>>>(dsys.p, umap.p);
   hchk(hipGetLastError(), "copy in");
-  for (auto& g : groups) {
+  // the groups' V-cycles and A z are independent: group 0 on the round's
+  // stream, every other group on a stream of its own, forked and joined by
+  // events (parallel branches of the captured graph)
+  hchk(hipEventRecord(fork_ev, s), "fork");
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    const hipStream_t st = gi == 0 ? s : g.stream;
+    if (gi > 0) hchk(hipStreamWaitEvent(st, fork_ev, 0), "fork");
     if (f32)
-      vcycle<float>(g);
+      vcycle<float>(g, st);
     else
-      vcycle<double>(g);
-  }
-  if (f32)
-    bcopy_out_kernel<float><<<grid, kThreads, 0, s>>>(dsys.p);
-  else
-    bcopy_out_kernel<double><<<grid, kThreads, 0, s>>>(dsys.p);
-  hchk(hipGetLastError(), "copy out");
-  for (auto& g : groups) {
-    for (int l = 1; l <= g.Lmax; ++l) {
-      const int first = (l + 1 <= g.Lmax) ? g.A[l + 1] : 0, cnt = g.A[l] - first;
-      if (cnt <= 0) continue;
-      const int Nl = 2 << l;
-      const int64_t nl = (int64_t)(g.k * Nl + 1) * (g.k * Nl + 1);
-      const auto& c64 = c0ip_internal_coef<double>(g.proto, l);
-      if (f32)
-        hchk(launch_apply2d<float, double>(g.k, Nl, c64, g.x32[l]->p + first * nl, nullptr, g.W[l]->p, s, cnt, nl,
-                                           g.mask.p + first),
-             "A z");
-      else
-        hchk(launch_apply2d<double, double>(g.k, Nl, c64, g.x64[l]->p + first * nl, nullptr, g.W[l]->p, s, cnt, nl,
-                                            g.mask.p + first),
-             "A z");
+      vcycle<double>(g, st);
+    az(g, st, f32);
+    if (gi > 0) {
+      hchk(hipEventRecord(g.join_ev, st), "join");
+      hchk(hipStreamWaitEvent(s, g.join_ev, 0), "join");
     }
   }
+  if (f32)
+    bcopy_out_kernel<float><<<gu, kThreads, 0, s>>>(dsys.p, umap.p);
+  else
+    bcopy_out_kernel<double><<<gu, kThreads, 0, s>>>(dsys.p, umap.p);
+  hchk(hipGetLastError(), "copy out");
   double vbytes = 0;
   for (auto& q : sys) vbytes += (double)q.n * m * sizeof(double);
   if (vbytes > 256.0 * (1 << 20))
-    bdots_kernel<true><<<dim3(maxblk, ns), kThreads, 0, s>>>(dsys.p, partial.p);
+    bdots_kernel<true><<<gd, kThreads, 0, s>>>(dsys.p, dmap.p, partial.p);
   else
-    bdots_kernel<false><<<dim3(maxblk, ns), kThreads, 0, s>>>(dsys.p, partial.p);
+    bdots_kernel<false><<<gd, kThreads, 0, s>>>(dsys.p, dmap.p, partial.p);
   hchk(hipGetLastError(), "dots");
   breduce_kernel<<<dim3(2 * m + 3, ns), kThreads, 0, s>>>(dsys.p, m, partial.p, hout.p);
   hchk(hipGetLastError(), "reduce");
   bcoef_kernel<<<(ns + 63) / 64, 64, 0, s>>>(dsys.p, ns, m, hout.p, coef.p);
   hchk(hipGetLastError(), "coef");
-  bupdate_kernel<<<grid, kThreads, 0, s>>>(dsys.p, m, coef.p);
+  bupdate_kernel<<<gu, kThreads, 0, s>>>(dsys.p, umap.p, m, coef.p);
   hchk(hipGetLastError(), "update");
   bgivens_kernel<<<ns, kThreads, 0, s>>>(dsys.p, m, hout.p, coef.p, dprm.p);
   hchk(hipGetLastError(), "givens");
@@ -776,7 +826,10 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
         g.W.back()->alloc((size_t)std::max(fin, 0) * nl);
       }
       g.mask.alloc(g.members.size());
+      hchk(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking), "stream");
+      hchk(hipEventCreateWithFlags(&g.join_ev, hipEventDisableTiming), "event");
     }
+    hchk(hipEventCreateWithFlags(&bt->fork_ev, hipEventDisableTiming), "event");
   } catch (const HErr& h) {
     return bfail(C0IP_EHIP, std::string(h.what) + ": " + hipGetErrorString(h.e));
   } catch (const std::bad_alloc&) {
@@ -906,11 +959,25 @@ c0ip_status c0ip_batch_solve(c0ip_batch* bt, const c0ip_krylov_opts* opts, const
       }
     }
     {
+      // partial-sum offsets and the block -> system maps of the Krylov grids
       int64_t off = 0;
+      std::vector<int> um, dm;
       for (int i = 0; i < ns; ++i) {
-        bt->hsys[i].poff = off;
-        off += (int64_t)(2 * m + 3) * bt->hsys[i].nblk;
+        KrySys& d = bt->hsys[i];
+        d.poff = off;
+        off += (int64_t)(2 * m + 3) * d.nblk;
+        d.d0 = (int)dm.size();
+        dm.insert(dm.end(), d.nblk, i);
+        d.u0 = (int)um.size();
+        um.insert(um.end(), (size_t)((d.n + kElBlock - 1) / kElBlock), i);
       }
+      bt->umap.alloc(um.size());
+      bt->dmap.alloc(dm.size());
+      hchk(hipMemcpy(bt->umap.p, um.data(), sizeof(int) * um.size(), hipMemcpyHostToDevice), "H2D");
+      hchk(hipMemcpy(bt->dmap.p, dm.data(), sizeof(int) * dm.size(), hipMemcpyHostToDevice), "H2D");
+      if ((int64_t)um.size() != bt->umap_n || (int64_t)dm.size() != bt->dmap_n) bt->graph_m = -1;  // grid sizes
+      bt->umap_n = (int64_t)um.size();
+      bt->dmap_n = (int64_t)dm.size();
     }
     for (auto& g : bt->groups) {  // group masks from the initial state
       std::vector<int> msk(g.members.size());
