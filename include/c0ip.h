@@ -142,6 +142,10 @@ typedef struct {
  * (omega 1/4 in 2D and 0.1 in 3D, 1 pre- and 1 post-step, float32
  * V-cycle, exact coarse solve, tail_levels -1, additive smoother with the
  * separable local solver).  hip_stream is a hipStream_t or NULL.
+ * Meshes whose vectors would hold 2^31 or more DoFs ((k N + 1)^d) are
+ * rejected with C0IP_EINVAL before any device call (the kernels index a
+ * vector's entries with 32-bit integers in places; at that size a float64
+ * Krylov basis would not fit in HBM anyway).
  * On success *out owns all device memory it allocated. */
 c0ip_status c0ip_create(const c0ip_mesh_desc* mesh, const c0ip_mg_opts* opts, void* hip_stream,
                         c0ip_problem** out);

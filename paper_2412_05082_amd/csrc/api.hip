@@ -544,6 +544,12 @@ c0ip_status check_mesh(const c0ip_mesh_desc* m) {
   if (m->degree < 2 || m->degree > 7) return fail(C0IP_EINVAL, "degree must be in [2,7]");
   if (!is_pow2(m->n_cells)) return fail(C0IP_EINVAL, "n_cells must be a power of two >= 2");
   if (m->n_cells > (1 << 16)) return fail(C0IP_EINVAL, "n_cells too large");
+  {
+    const int64_t n1 = (int64_t)m->degree * m->n_cells + 1;
+    const int64_t nv = m->dim == 2 ? n1 * n1 : n1 * n1 * n1;
+    if (nv >= (int64_t(1) << 31))
+      return fail(C0IP_EINVAL, "mesh too large: " + std::to_string(nv) + " DoFs per vector (at most 2^31 - 1)");
+  }
   return C0IP_OK;
 }
 

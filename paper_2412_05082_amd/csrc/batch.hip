@@ -735,6 +735,15 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
     return bfail(C0IP_EUNSUPPORTED, "batched solves use the additive smoother (smoother 0)");
   if (mg.local_solver != 0)
     return bfail(C0IP_EUNSUPPORTED, "batched solves use the separable local solver (local_solver 0)");
+  for (int i = 0; i < n_problems; ++i) {  // every mesh, before any device call
+    const c0ip_mesh_desc& md = meshes[i];
+    if (md.dim != 2) return bfail(C0IP_EUNSUPPORTED, "batches are built for 2D meshes");
+    if (n_rhs[i] < 1 || n_rhs[i] > 4096) return bfail(C0IP_EINVAL, "n_rhs must be in [1, 4096]");
+    if (md.degree < 2 || md.degree > 7 || md.n_cells < 2 || (md.n_cells & (md.n_cells - 1)) ||
+        md.n_cells > (1 << 16) ||
+        ((int64_t)md.degree * md.n_cells + 1) * ((int64_t)md.degree * md.n_cells + 1) >= (int64_t(1) << 31))
+      return bfail(C0IP_EINVAL, "bad mesh in batch (degree 2..7, n_cells a power of two, < 2^31 DoFs)");
+  }
   std::unique_ptr<c0ip_batch> bt(new c0ip_batch());
   bt->mg = mg;
   bt->user = (hipStream_t)hip_stream;
@@ -743,10 +752,6 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
     // systems
     for (int i = 0; i < n_problems; ++i) {
       const c0ip_mesh_desc& md = meshes[i];
-      if (md.dim != 2) return bfail(C0IP_EUNSUPPORTED, "batches are built for 2D meshes");
-      if (n_rhs[i] < 1 || n_rhs[i] > 4096) return bfail(C0IP_EINVAL, "n_rhs must be in [1, 4096]");
-      if (md.degree < 2 || md.degree > 7 || md.n_cells < 2 || (md.n_cells & (md.n_cells - 1)))
-        return bfail(C0IP_EINVAL, "bad mesh in batch");
       bt->meshes.push_back(md);
       bt->nrhs.push_back(n_rhs[i]);
       const double gam = md.gamma > 0 ? md.gamma : (double)(md.degree * (md.degree + 1));

@@ -117,3 +117,21 @@ def test_host_entry_points_reject_bad_arguments():
         P.host_patch_inverse(2, 3, 4, [0, 1])
     with pytest.raises(P.C0ipError):
         P.host_patch_inverse(2, 3, 6, [1, 1])  # not a power of two
+
+
+def test_meshes_beyond_the_dof_limit_are_rejected_before_any_device_call():
+    """(k N + 1)^d >= 2^31 DoFs per vector is refused with C0IP_EINVAL by
+    c0ip_create and c0ip_batch_create (no GPU needed to see it); the largest
+    accepted meshes are exercised by the GPU maximum-size tests."""
+    import ctypes as C
+    lib = P.load_library()
+    h = C.c_void_p()
+    for dim, N, k in [(2, 16384, 3), (2, 65536, 2), (3, 1024, 2), (3, 512, 3)]:
+        n1 = k * N + 1
+        assert n1 ** dim >= 2 ** 31
+        mesh = P.MeshDesc(dim, N, k, 0.0)
+        assert lib.c0ip_create(C.byref(mesh), None, None, C.byref(h)) == -1, (dim, N, k)
+        assert b"too large" in lib.c0ip_last_error()
+    meshes = (P.MeshDesc * 1)(P.MeshDesc(2, 16384, 3, 0.0))
+    rhs = (C.c_int * 1)(1)
+    assert lib.c0ip_batch_create(meshes, rhs, 1, None, None, C.byref(h)) == -1
