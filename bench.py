@@ -27,6 +27,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector FP64 / FP32
+
+
+def binding_roofline(P, dim, k, N, kind, prec, dofs_per_s):
+    """Achieved fraction of the kernel's binding roofline, min(HBM, compute),
+    from algorithmic bytes and FMAs per DoF.  Operator: per DoF the x, y
+    (and z) passes of the Kronecker sum, 4m + 2b FMAs in 2D and 9m + 3b in
+    3D, with m and b the mean row nonzeros of the global 1D mass/Laplace and
+    bi-Laplace matrices (counted from the library's own 1D factors).  Patch
+    solves by fast diagonalisation: 2d passes of n^(d+1) products plus the
+    n^d scalings per patch, (N-1)^d patches.  A smoother step adds one
+    operator apply (the residual)."""
+    import numpy as np
+    M, L, B = P.host_matrices_1d(k, N)
+    inner = slice(1, M.shape[0] - 1)  # boundary rows are identity rows
+    m = float(np.count_nonzero(M[inner], axis=1).mean())
+    b = float(np.count_nonzero(B[inner], axis=1).mean())
+    n_t = (k * N + 1) ** dim
+    n = 2 * k - 1
+    fma = 4 * m + 2 * b if dim == 2 else 9 * m + 3 * b
+    if kind != "mv":
+        fma += (2 * dim * n ** (dim + 1) + n ** dim) * (N - 1) ** dim / n_t
+    byt = {"mv": 16, "sm": 24}[kind] // (2 if prec == "f32" else 1)
+    hbm = HBM_PEAK_GBS * 1e9 / byt
+    alu = VALU_PEAK_TFLOPS[prec] * 1e12 / (2 * fma)
+    bound = "hbm" if hbm <= alu else "alu"
+    return {"bound": bound, "fma_per_dof": fma, "roof_dofs_per_s": min(hbm, alu),
+            "frac_binding": dofs_per_s / min(hbm, alu)}
 
 
 def parse():
@@ -252,6 +280,8 @@ def bench_3d(args, torch, P):
     for name, ms, byt in [("matvec_f64", ms_mv, 16), ("smoother_f64", ms_sm, 24), ("matvec_f32", ms_mv32, 8),
                           ("smoother_f32", ms_sm32, 12)]:
         out[name] = {"ms": ms, "dofs_per_s": n / (ms * 1e-3), "alg_GBs": byt * n / (ms * 1e-3) / 1e9}
+        out[name].update(binding_roofline(P, 3, 3, 128, "mv" if name.startswith("matvec") else "sm",
+                                          name[-3:], out[name]["dofs_per_s"]))
     return out
 
 
@@ -373,6 +403,10 @@ def bench_sweep(args, torch, P):
         row["kernels"] = {kname: {"ms": v, "dofs_per_s": n / (v * 1e-3),
                                   "alg_GBs": {"matvec_f64": 16, "smoother_f64": 24, "smoother_f32": 12}[kname] * n /
                                   (v * 1e-3) / 1e9} for kname, v in ms.items()}
+        for kname, kind, prec in [("matvec_f64", "mv", "f64"), ("smoother_f64", "sm", "f64"),
+                                  ("smoother_f32", "sm", "f32")]:
+            row["kernels"][kname].update(
+                binding_roofline(P, 2, k, N, kind, prec, row["kernels"][kname]["dofs_per_s"]))
         row["kernels"]["smoother_f32_variant"] = pk.tuned_variant(dtype=P.C0IP_F32)
         del sets, xk
         pk.close()
@@ -630,6 +664,9 @@ def main():
                                f"S(x,b) (residual in LDS + patch solves), 12 B/DoF x {n} DoFs per launch; "
                                f"traffic = HBM bytes per launch from FETCH_SIZE/WRITE_SIZE"},
     }
+    for kname, kind, prec in [("matvec_f64", "mv", "f64"), ("smoother_f64", "sm", "f64"), ("matvec_f32", "mv", "f32"),
+                              ("smoother_f32", "sm", "f32")]:
+        out["kernels"][kname].update(binding_roofline(P, dim, k, N, kind, prec, out["kernels"][kname]["dofs_per_s"]))
     if not args.no_extra:
         out.update(bench_extra(args, torch, P, b, x_np))
         progress("extra C2 legs done")
