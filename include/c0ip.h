@@ -130,10 +130,9 @@ typedef struct {
   double rel_res_est;  /* final Arnoldi estimate / ||b|| */
   double rel_res_true; /* ||b - A x|| / ||b|| recomputed in float64 */
   double frac_iters;   /* 8 n / (-log10(rel_res_est)) (Sec. 5.1) */
-  /* wall time of the solve; time in the V-cycles (c0ip_solve: events on
-   * every 8th iteration, scaled to all iterations; c0ip_solve_fcg: every
-   * iteration); the rest (A z, the Krylov vector passes and reductions, the
-   * host's Hessenberg work, restarts) */
+  /* wall time of the solve; time in the V-cycles (events on every 8th
+   * iteration, scaled to all iterations); the rest (A z, the Krylov vector
+   * passes and reductions, the host's Hessenberg work, restarts) */
   double seconds_total, seconds_vcycle, seconds_arnoldi;
 } c0ip_solve_info;
 

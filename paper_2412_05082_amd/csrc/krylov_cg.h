@@ -27,9 +27,10 @@ hipError_t launch_reduce(int m, int nblk, const double* partial, double* sc, int
 // p = z - beta p  (beta = sc[kBETA]; first = 1: p = z)
 template <typename Tz>
 hipError_t launch_update_p(int64_t n, const Tz* z, const double* sc, double* p, int first, hipStream_t s);
-// x += alpha p, r -= alpha q (alpha = sc[kALPHA]); partial[b] = block b's share of r . r
+// x += alpha p, r -= alpha q (alpha = sc[kALPHA]); partial[b] = block b's share of r . r;
+// r32: NULL, or receives (float) of the new r (the next float32 V-cycle's input)
 hipError_t launch_update_xr(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
-                            double* partial, int nblk, hipStream_t s);
+                            double* partial, int nblk, hipStream_t s, float* r32 = nullptr);
 
 }  // namespace cg
 }  // namespace c0ip

@@ -96,7 +96,8 @@ __global__ __launch_bounds__(kThreads) void update_p_kernel(int64_t n, const Tz*
 __global__ __launch_bounds__(kThreads) void update_xr_kernel(int64_t n, const double* __restrict__ sc,
                                                              const double* __restrict__ p,
                                                              const double* __restrict__ q, double* __restrict__ x,
-                                                             double* __restrict__ r, double* __restrict__ partial) {
+                                                             double* __restrict__ r, double* __restrict__ partial,
+                                                             float* __restrict__ r32) {
   __shared__ double red[kThreads / 64];
   const double alpha = sc[kALPHA];
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(int64_t n, const do
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
+    if (r32) r32[i] = (float)ri;
     a += ri * ri;
   }
   const double t = block_sum(a, red);
@@ -153,8 +155,8 @@ hipError_t launch_update_p(int64_t n, const Tz* z, const double* sc, double* p, 
 }
 
 hipError_t launch_update_xr(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
-                            double* partial, int nblk, hipStream_t s) {
-  update_xr_kernel<<<nblk, kThreads, 0, s>>>(n, sc, p, q, x, r, partial);
+                            double* partial, int nblk, hipStream_t s, float* r32) {
+  update_xr_kernel<<<nblk, kThreads, 0, s>>>(n, sc, p, q, x, r, partial, r32);
   return hipGetLastError();
 }
 
