@@ -113,9 +113,10 @@ struct c0ip_problem {
   DevBuf<float> cg_z32;
   double* hpin = nullptr;  // pinned host staging for the per-step reductions
   // The V-cycle of the Krylov solves as a captured graph, per precision
-  // ([0] float64, [1] float32): input u (float64; the float32 graph starts
-  // with the cast), output zfix.  Captured on first use and again when the
-  // buffers or a tile variant changed.
+  // ([0] float64, [1] float32; used when C0IP_VCYCLE_GRAPH=1): input u
+  // (float64), or for float32 the finest level's b (u == NULL) or u cast
+  // into it by the graph's first launch; output zfix.  Captured on first use
+  // and again when the buffers or a tile variant changed.
   struct VGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

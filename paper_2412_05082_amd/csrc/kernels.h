@@ -64,17 +64,12 @@ hipError_t launch_multidot(int64_t n, int m, const double* V, int64_t ldv, const
 // out[j] = sum_b partial[j * nblk + b] (+ out_add[j] if accumulate)
 hipError_t launch_reduce_partials(int m, int nblk, const double* partial, double* out, int accumulate,
                                   hipStream_t s);
-// w -= sum_j h[j] V_j   (h on the device)
-hipError_t launch_multiaxpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* w,
-                            hipStream_t s);
 // v = w / *nrm (nrm = device pointer to a squared norm: v = w / sqrt(*nrm))
 hipError_t launch_normalize(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t s);
 // x += sum_j y[j] Z_j  (Z of type Tz)
 template <typename Tz>
 hipError_t launch_update_solution(int64_t n, int m, const Tz* Z, int64_t ldz, const double* y, double* x,
                                   hipStream_t s);
-// flags[0] |= any non-finite in a
-hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s);
 
 int multidot_blocks(int64_t n);
 

@@ -279,22 +279,6 @@ __global__ __launch_bounds__(kThreads) void reduce_partials_kernel(int nblk, con
   }
 }
 
-__global__ __launch_bounds__(kThreads) void multiaxpy_kernel(int64_t n, int m, const double* __restrict__ V,
-                                                             int64_t ldv, const double* __restrict__ h,
-                                                             double* __restrict__ w) {
-  __shared__ double sh[kMaxDot];
-  for (int j0 = 0; j0 < m; j0 += kMaxDot) {
-    const int mj = min(kMaxDot, m - j0);
-    __syncthreads();
-    if (threadIdx.x < mj) sh[threadIdx.x] = h[j0 + threadIdx.x];
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-      double s = w[i];
-      for (int j = 0; j < mj; ++j) s -= sh[j] * V[(int64_t)(j0 + j) * ldv + i];
-      w[i] = s;
-    }
-  }
-}
 
 __global__ __launch_bounds__(kThreads) void normalize_kernel(int64_t n, const double* __restrict__ w,
                                                              const double* __restrict__ nrm2,
@@ -322,13 +306,6 @@ __global__ __launch_bounds__(kThreads) void update_solution_kernel(int64_t n, in
   }
 }
 
-__global__ __launch_bounds__(kThreads) void check_finite_kernel(int64_t n, const double* __restrict__ a,
-                                                                int* __restrict__ flag) {
-  int bad = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-    bad |= !isfinite(a[i]);
-  if (bad) atomicOr(flag, 1);
-}
 
 // ---- Arnoldi step with delayed re-orthogonalisation (classical Gram-Schmidt
 // applied twice, the second pass of vector j fused into step j+1).
@@ -584,11 +561,6 @@ hipError_t launch_reduce_partials(int m, int nblk, const double* partial, double
   return hipGetLastError();
 }
 
-hipError_t launch_multiaxpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* w,
-                            hipStream_t s) {
-  multiaxpy_kernel<<<grid_for(n), kThreads, 0, s>>>(n, m, V, ldv, h, w);
-  return hipGetLastError();
-}
 
 hipError_t launch_normalize(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t s) {
   normalize_kernel<<<grid_for(n), kThreads, 0, s>>>(n, w, nrm2, v);
@@ -630,10 +602,6 @@ hipError_t launch_arnoldi_update(int64_t n, int j, const double* V, int64_t ldv,
   return hipGetLastError();
 }
 
-hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s) {
-  check_finite_kernel<<<grid_for(n), kThreads, 0, s>>>(n, a, flag);
-  return hipGetLastError();
-}
 
 template hipError_t launch_apply<double, double>(int, int, int, const LevelCoef<double>&, const double*,
                                                  const double*, double*, hipStream_t);
