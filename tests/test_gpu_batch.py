@@ -121,6 +121,32 @@ def test_batch_zero_rhs_and_initial_guess():
     assert np.linalg.norm(host(xs[1][0]) - host(xr1)) <= 1e-10 * np.linalg.norm(host(xr1))
 
 
+def test_batch_non_finite_system_then_clean_solve():
+    """A NaN in one system's right-hand side makes the batched solve return
+    C0IP_ENAN (the other systems still finish); the same batch then solves
+    clean right-hand sides with the single solves' iterations."""
+    say("batch non-finite then clean")
+    probs, nrhs = [(16, 3), (8, 2)], [2, 1]
+    bt = P.Batch(probs, nrhs, omega=0.25)
+    bs = [torch.from_numpy(_rhs(N, k, r, 60 + i)).cuda() for i, ((N, k), r) in enumerate(zip(probs, nrhs))]
+    bad = [b.clone() for b in bs]
+    bad[0][1, 100] = float("nan")
+    xs = [torch.zeros_like(b) for b in bs]
+    with pytest.raises(P.C0ipError) as e:
+        bt.solve(bad, xs)
+    assert e.value.status == -5
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = bt.solve(bs, xs)
+    t = 0
+    for i, ((N, k), r) in enumerate(zip(probs, nrhs)):
+        pb = P.Problem(2, N, k, omega=0.25)
+        for q in range(r):
+            xr = torch.zeros_like(bs[i][q])
+            info = pb.solve(bs[i][q].contiguous(), xr)
+            assert infos[t]["converged"] == 1 and infos[t]["iterations"] == info["iterations"], (i, q)
+            t += 1
+
+
 def test_batch_rejects_3d_and_bad_shapes():
     lib = P.load_library()
     with pytest.raises(P.C0ipError):
