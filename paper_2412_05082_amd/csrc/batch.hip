@@ -639,7 +639,7 @@ void c0ip_batch::vcycle(Group& g, hipStream_t gs) {
 
 // A z for every system of the group, at each system's finest level, into W.
 void c0ip_batch::az(Group& g, hipStream_t st, bool f32) {
-  for (int l = 1; l <= g.Lmax; ++l) {
+  for (int l = 0; l <= g.Lmax; ++l) {  // level 0 too: meshes of 2 x 2 cells
     const int first = (l + 1 <= g.Lmax) ? g.A[l + 1] : 0, cnt = g.A[l] - first;
     if (cnt <= 0) continue;
     const int Nl = 2 << l;

@@ -147,6 +147,32 @@ def test_batch_non_finite_system_then_clean_solve():
             t += 1
 
 
+def test_batch_degenerate_meshes_and_restart_one():
+    """Degenerate cases: meshes of 2 x 2 cells (the coarse level alone, one
+    vertex patch) next to a 4 x 4 mesh, and FGMRES(1) stopped by max_iters;
+    batched and single solves agree on iterations, status and solution."""
+    say("batch degenerate")
+    probs, nrhs = [(2, 2), (2, 3), (4, 2), (8, 3)], [1, 2, 1, 1]
+    bs = [torch.from_numpy(_rhs(N, k, r, 80 + i)).cuda() for i, ((N, k), r) in enumerate(zip(probs, nrhs))]
+    for restart, max_iters in [(50, 500), (1, 6)]:
+        bt = P.Batch(probs, nrhs, omega=0.25)
+        xs = [torch.zeros_like(b) for b in bs]
+        infos = bt.solve(bs, xs, restart=restart, max_iters=max_iters, raise_on_nonconv=False)
+        t = 0
+        for i, ((N, k), r) in enumerate(zip(probs, nrhs)):
+            pb = P.Problem(2, N, k, omega=0.25)
+            for q in range(r):
+                xr = torch.zeros_like(bs[i][q])
+                info = pb.solve(bs[i][q].contiguous(), xr, restart=restart, max_iters=max_iters,
+                                raise_on_nonconv=False)
+                assert infos[t]["iterations"] == info["iterations"], (restart, i, q, infos[t], info)
+                assert infos[t]["converged"] == info["converged"], (restart, i, q)
+                xb, xh = host(xs[i][q]), host(xr)
+                assert np.linalg.norm(xb - xh) <= 1e-10 * max(np.linalg.norm(xh), 1e-300), (restart, i, q)
+                t += 1
+        bt.close()
+
+
 def test_batch_rejects_3d_and_bad_shapes():
     lib = P.load_library()
     with pytest.raises(P.C0ipError):
