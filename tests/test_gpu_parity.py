@@ -119,7 +119,8 @@ def test_vcycle_f64_matches_oracle(dim, k, N):
     check("vcycle f64", rel_l2(host(xd), ref), fp64_vcycle_tol(dim, k, N))
 
 
-@pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 3, 64), (2, 4, 32)])
+@pytest.mark.parametrize("dim,k,N", [(2, 2, 16), (2, 3, 16), (2, 3, 64), (2, 4, 32), (2, 5, 8), (2, 6, 8),
+                                     (2, 7, 8), (2, 7, 16)])
 def test_vcycle_f32_matches_oracle(dim, k, N):
     say("vcycle f32", dim, k, N)
     H = O.Hierarchy(dim, k, N, omega=0.25)
