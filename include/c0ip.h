@@ -100,7 +100,15 @@ typedef struct {
  *   per patch boundary type, float64 Cholesky, rounded for float32) and
  *   applied as a dense product.  1 is built for 2D meshes with scatter_mode
  *   0 (C0IP_EUNSUPPORTED otherwise, and for batched solves).  Other values:
- *   C0IP_EINVAL. */
+ *   C0IP_EINVAL.
+ * mvs_residual: where a 2D multiplicative step forms each colour's
+ *   residual b - A x.  1 = in the colour's own launch, on its patches'
+ *   rows only (x staged in LDS around each patch); 2 = a full residual pass
+ *   with the tiled operator before each colour's solves; 0 = automatic (1 on
+ *   levels under 2^20 DoFs, where launches dominate, 2 on finer ones).  The
+ *   modes give the same result (the same sums in the same order).  Ignored
+ *   in 3D (always 2) and by the additive smoother; batched solves take 0
+ *   only.  Other values: C0IP_EINVAL. */
 typedef struct {
   double omega;
   int pre_steps, post_steps;
@@ -110,6 +118,7 @@ typedef struct {
   int tail_levels;
   int smoother;
   int local_solver;
+  int mvs_residual;
 } c0ip_mg_opts;
 
 /* Flexible GMRES options (Sec. 5.1: relative residual reduction 1e-8).

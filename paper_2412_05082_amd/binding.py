@@ -29,7 +29,8 @@ class MeshDesc(C.Structure):
 class MgOpts(C.Structure):
     _fields_ = [("omega", C.c_double), ("pre_steps", C.c_int), ("post_steps", C.c_int),
                 ("vcycle_dtype", C.c_int), ("coarse_mode", C.c_int), ("scatter_mode", C.c_int),
-                ("tail_levels", C.c_int), ("smoother", C.c_int), ("local_solver", C.c_int)]
+                ("tail_levels", C.c_int), ("smoother", C.c_int), ("local_solver", C.c_int),
+                ("mvs_residual", C.c_int)]
 
 
 class KrylovOpts(C.Structure):
@@ -120,15 +121,17 @@ class Problem:
 
     def __init__(self, dim, n_cells, degree, gamma=0.0, omega=None, pre_steps=1, post_steps=1,
                  vcycle_dtype=C0IP_F32, coarse_mode=0, scatter_mode=0, tail_levels=-1, smoother=0, local_solver=0,
-                 stream=None):
+                 mvs_residual=0, stream=None):
         """smoother: 0 = additive (AVS), 1 = coloured multiplicative (MVS);
-        local_solver: 0 = separable (fast diagonalisation), 1 = exact (dense)."""
+        local_solver: 0 = separable (fast diagonalisation), 1 = exact (dense);
+        mvs_residual: 2D MVS residual per colour, 0 = automatic, 1 = in the
+        colour launch, 2 = a full residual pass."""
         lib = load_library()
         if omega is None:
             omega = 0.25 if dim == 2 else 0.1
         self.mesh = MeshDesc(dim, n_cells, degree, gamma)
         self.mg = MgOpts(omega, pre_steps, post_steps, vcycle_dtype, coarse_mode, scatter_mode, tail_levels,
-                         smoother, local_solver)
+                         smoother, local_solver, mvs_residual)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

@@ -728,7 +728,9 @@ c0ip_status c0ip_batch_create(const c0ip_mesh_desc* meshes, const int* n_rhs, in
     mg.tail_levels = -1;
     mg.smoother = 0;
     mg.local_solver = 0;
+    mg.mvs_residual = 0;
   }
+  if (mg.mvs_residual != 0) return bfail(C0IP_EUNSUPPORTED, "batched solves take mvs_residual 0");
   if (mg.scatter_mode != 0)
     return bfail(C0IP_EUNSUPPORTED, "batched solves use the owner-computes smoother (scatter_mode 0)");
   if (mg.smoother != 0)

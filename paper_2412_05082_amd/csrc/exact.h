@@ -14,9 +14,6 @@ namespace c0ip {
 template <typename T>
 hipError_t launch_patch2d_exact(int k, int N, const T* Aex, const T* r, const T* xin, T* xout, T omega,
                                 hipStream_t s);
-// One colour of the coloured multiplicative smoother with exact local solves (in place on x).
-template <typename T>
-hipError_t launch_mvs2d_colour_exact(int k, int N, int colour, const T* Aex, const T* r, T* x, T omega,
-                                     hipStream_t s);
+// One colour of the multiplicative smoother with exact local solves: launch_mvs2d_colour_exact (kernels.h).
 
 }  // namespace c0ip

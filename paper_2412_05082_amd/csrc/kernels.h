@@ -104,11 +104,19 @@ hipError_t launch_patch2d(int k, int N, const LevelEig<T>& e, const T* r, const 
 template <typename T>
 hipError_t launch_patch2d_atomic(int k, int N, const LevelEig<T>& e, const T* r, T* xout, T omega, hipStream_t s);
 // One colour of the coloured multiplicative smoother (2D, 8 colours):
-// x += omega * sum over the colour's patches of R_v^T A~_v^{-1} R_v r, in
-// place (the colour's patches are disjoint and A-orthogonal).
+// One colour of the 2D multiplicative smoother, in place on x:
+// x += omega * sum over the colour's patches of R_v^T A~_v^{-1} R_v r.  With
+// r == nullptr the launch forms r = b - A x on each patch's rows in LDS,
+// from x as it is before the launch (the colour's patches are disjoint and
+// A-orthogonal, and none reads the nodes another one writes); else r is
+// read (a residual computed beforehand, or b when x is 0).
 template <typename T>
-hipError_t launch_mvs2d_colour(int k, int N, int colour, const LevelEig<T>& e, const T* r, T* x, T omega,
-                               hipStream_t s);
+hipError_t launch_mvs2d_colour(int k, int N, int colour, const LevelCoef<T>& c, const LevelEig<T>& e, const T* b,
+                               const T* r, T* x, T omega, hipStream_t s);
+// The same with exact local solves (dense inverses Aex, layout as in exact.h).
+template <typename T>
+hipError_t launch_mvs2d_colour_exact(int k, int N, int colour, const LevelCoef<T>& c, const T* Aex, const T* b,
+                                     const T* r, T* x, T omega, hipStream_t s);
 // One fused smoothing step S(x, b) (residual in LDS; x_out must not alias x).
 // variant: tile-size variant (0 = default; see avs2d_variants).  With ec:
 // the step starts from x + P ec instead (ec: coarse vector of the level

@@ -433,27 +433,118 @@ __device__ __forceinline__ void colour_vertex(const ColourRows& cr, int px, int 
   vy = 2 * b + py;
 }
 
-template <int K> struct ColourPatches { static constexpr int NPW = kThreads / (2 * K - 1); };
+// Patches per workgroup of the colour kernel and its LDS strips.  A patch's
+// residual rows (its (2k-1)^2 interior nodes) reach, through the bands of
+// the 1D factors, the nodes of the patch's cells (M, L: 2k+1 per axis) and
+// of the cells next to them (B: 4k+1 per axis).  The operator is
+// M_y (X B_x) + 2 L_y (X L_x) + B_y (X M_x), so two strips of x suffice:
+// the patch rows over 4k+1 columns (for X B_x and X L_x) and 4k+1 rows over
+// the patch columns (for X M_x).  Neither strip holds a node interior to
+// another patch of the colour: patches of one colour are 4 cells apart
+// along an axis or 2 cells apart along both, so their interiors never fall
+// inside the closed patch rows or columns.  NP patches fill a workgroup
+// with one local-solve output per thread; the coefficient table (at most
+// 5k+2 row classes) is staged in LDS.
+template <int K>
+struct ColourFused {
+  static constexpr int n = 2 * K - 1, NN = n * n, C = 2 * K + 1, W = 4 * K + 1, R = C * W;
+  static constexpr int NP = kThreads / NN > 0 ? kThreads / NN : 1;
+  static constexpr int MAXCLASS = 5 * K + 2, TAB = 3 * MAXCLASS * W;
+};
 
+// Band product of factor OP for a row of class cl at cell position p (sTab:
+// the table in LDS); v points at the row's own tap, taps `stride` apart.
+template <typename T, int OP, int K>
+__device__ __forceinline__ T colour_band(const T* sTab, int nclass, int cl, int p, const T* v, int stride) {
+  const T* c = sTab + (OP * nclass + cl) * (4 * K + 1) + 2 * K;
+  T a = 0;
+  for (int o = tile::Band<OP, K>::lo(p); o <= tile::Band<OP, K>::hi(p); ++o) a += c[o] * v[o * stride];
+  return a;
+}
+
+// x <- x + omega * sum over the colour's patches of R_v^T A~_v^{-1} R_v r
+// (or of R_v^T A_v^{-1} R_v r with the exact local matrices), r = b - A x
+// formed on the patch rows in LDS, or read from rsrc when that is given (a
+// residual computed beforehand, or b when x is 0).
 template <typename T, int K, bool EXACT>
-__global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restrict__ r, T* __restrict__ x, int N,
+__global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restrict__ b, T* __restrict__ x, int N,
                                                                 int n1, ColourRows cr, int px, int py,
+                                                                const T* __restrict__ tab, int nclass, int left,
+                                                                int right0, int periodic, const T* __restrict__ rsrc,
                                                                 const T* __restrict__ Qg, const T* __restrict__ lamg,
                                                                 const T* __restrict__ Aex, T omega) {
-  constexpr int n = 2 * K - 1, NN = n * n, NPW = ColourPatches<K>::NPW;
-  __shared__ T sA[NPW * NN];
-  __shared__ T sB[NPW * NN];
-  __shared__ T sQ[4 * NN];
-  __shared__ T sLam[4 * n];
-  const int q0 = blockIdx.x * NPW;
-  const int np = min(NPW, cr.total - q0);
+  using F = ColourFused<K>;
+  constexpr int n = F::n, NN = F::NN, C = F::C, W = F::W, R = F::R, NP = F::NP;
+  __shared__ T sRow[NP * R];   // rows (vy-1)K .. (vy+1)K, columns (vx-2)K .. (vx+2)K
+  __shared__ T sCol[NP * R];   // rows (vy-2)K .. (vy+2)K, columns (vx-1)K .. (vx+1)K
+  __shared__ T sTB[NP * C * n];
+  __shared__ T sTL[NP * C * n];
+  __shared__ T sTM[NP * W * n];
+  __shared__ T sA[NP * NN];
+  __shared__ T sB[NP * NN];
+  __shared__ T sTab[F::TAB];
+  __shared__ T sQ[EXACT ? 1 : 4 * NN];
+  __shared__ T sLam[EXACT ? 1 : 4 * n];
+  const int q0 = blockIdx.x * NP;
+  const int np = min(NP, cr.total - q0);
   if (np <= 0) return;
-  // gather r on the patches' nodes (rows of n consecutive nodes)
-  for (int e = threadIdx.x; e < np * NN; e += kThreads) {
-    const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
-    int vx, vy;
-    colour_vertex(cr, px, py, q0 + p, vx, vy);
-    sB[e] = r[(size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c];
+  if (rsrc) {
+    for (int e = threadIdx.x; e < np * NN; e += kThreads) {
+      const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
+      int vx, vy;
+      colour_vertex(cr, px, py, q0 + p, vx, vy);
+      sB[e] = rsrc[(size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c];
+    }
+  } else {
+    // stage the two strips of x (zero outside the mesh) and the table
+    for (int e = threadIdx.x; e < np * R; e += kThreads) {
+      const int p = e / R, loc = e - p * R;
+      int vx, vy;
+      colour_vertex(cr, px, py, q0 + p, vx, vy);
+      {
+        const int i = loc / W, j = loc - i * W;
+        const int gy = (vy - 1) * K + i, gx = (vx - 2) * K + j;
+        sRow[e] = (gx >= 0 && gx < n1) ? x[(size_t)gy * n1 + gx] : T(0);
+      }
+      {
+        const int i = loc / C, j = loc - i * C;
+        const int gy = (vy - 2) * K + i, gx = (vx - 1) * K + j;
+        sCol[e] = (gy >= 0 && gy < n1) ? x[(size_t)gy * n1 + gx] : T(0);
+      }
+    }
+    for (int e = threadIdx.x; e < 3 * nclass * W; e += kThreads) sTab[e] = tab[e];
+    __syncthreads();
+    // x passes at the patch's interior columns: X B_x and X L_x on the patch
+    // rows, X M_x on 4K+1 rows (items ordered column-major, so that the
+    // lanes of a wave mostly share a column and its band extent)
+    for (int e = threadIdx.x; e < np * (C + W) * n; e += kThreads) {
+      const int c = e / (np * (C + W)), rem = e - c * (np * (C + W)), p = rem / (C + W), i = rem - p * (C + W);
+      int vx, vy;
+      colour_vertex(cr, px, py, q0 + p, vx, vy);
+      const int gx = (vx - 1) * K + 1 + c, pc = (1 + c) % K;
+      const int cl = tile::row_class(gx, n1, K, left, right0, periodic);
+      if (i < C) {
+        const T* v = sRow + p * R + i * W + K + 1 + c;
+        sTB[(p * C + i) * n + c] = colour_band<T, 2, K>(sTab, nclass, cl, pc, v, 1);
+        sTL[(p * C + i) * n + c] = colour_band<T, 1, K>(sTab, nclass, cl, pc, v, 1);
+      } else {
+        const int iw = i - C;
+        sTM[(p * W + iw) * n + c] = colour_band<T, 0, K>(sTab, nclass, cl, pc, sCol + p * R + iw * C + 1 + c, 1);
+      }
+    }
+    __syncthreads();
+    // y passes: r = b - (M_y TB + 2 L_y TL + B_y TM) at the patch's interior rows (row-major items)
+    for (int e = threadIdx.x; e < np * NN; e += kThreads) {
+      const int a = e / (np * n), rem = e - a * (np * n), p = rem / n, c = rem - p * n;
+      int vx, vy;
+      colour_vertex(cr, px, py, q0 + p, vx, vy);
+      const int gy = (vy - 1) * K + 1 + a, pa = (1 + a) % K;
+      const int cl = tile::row_class(gy, n1, K, left, right0, periodic);
+      const T ax = colour_band<T, 0, K>(sTab, nclass, cl, pa, sTB + (p * C + 1 + a) * n + c, n) +
+                   T(2) * colour_band<T, 1, K>(sTab, nclass, cl, pa, sTL + (p * C + 1 + a) * n + c, n) +
+                   colour_band<T, 2, K>(sTab, nclass, cl, pa, sTM + (p * W + K + 1 + a) * n + c, n);
+      sB[p * NN + a * n + c] = b[(size_t)gy * n1 + (vx - 1) * K + 1 + c] - ax;
+    }
   }
   if constexpr (EXACT) {
     // exact local solves: u = A_v^{-1} r_v, one dense row per thread and patch
@@ -468,109 +559,74 @@ __global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restr
       for (int j = 0; j < NN; ++j) s += row[j] * rv[j];
       sA[it] = s;
     }
+  } else {
+    // fast diagonalisation, one output per thread and stage:
+    // r (sB) -> Q_x^T along x (sA) -> Q_y^T along y, / (lambda_x + lambda_y) (sB)
+    //        -> Q_y along y (sA) -> Q_x along x (sB)
+    for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
+    for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
     __syncthreads();
-    for (int e = threadIdx.x; e < np * NN; e += kThreads) {
-      const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
-      int vx, vy;
-      colour_vertex(cr, px, py, q0 + p, vx, vy);
-      const size_t g = (size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c;
-      x[g] = x[g] + omega * sA[e];
-    }
-    return;
-  }
-  for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
-  for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
-  __syncthreads();
-  // forward along x: t[a][c] = sum_c' Qx[c'][c] r[a][c']
-  for (int it = threadIdx.x; it < np * n; it += kThreads) {
-    const int p = it / n, a = it - p * n;
-    int vx, vy;
-    colour_vertex(cr, px, py, q0 + p, vx, vy);
-    const T* qx = sQ + variant(vx, N) * NN;
-    T in[n];
-#pragma unroll
-    for (int c = 0; c < n; ++c) in[c] = sB[p * NN + a * n + c];
-#pragma unroll
-    for (int c = 0; c < n; ++c) {
-      T s = 0;
-#pragma unroll
-      for (int cp = 0; cp < n; ++cp) s += qx[cp * n + c] * in[cp];
-      sA[p * NN + a * n + c] = s;
-    }
-  }
-  __syncthreads();
-  // along y: forward with Qy^T, divide by lambda_x + lambda_y, back with Qy
-  for (int it = threadIdx.x; it < np * n; it += kThreads) {
-    const int p = it / n, c = it - p * n;
-    int vx, vy;
-    colour_vertex(cr, px, py, q0 + p, vx, vy);
-    const int ty = variant(vy, N), tx = variant(vx, N);
+    const int e = threadIdx.x;
+    const bool on = e < np * NN;
+    const int p = on ? e / NN : 0, loc = e - p * NN, a = loc / n, c = loc - a * n;
+    int vx = 1, vy = 1;
+    if (on) colour_vertex(cr, px, py, q0 + p, vx, vy);
+    const int tx = variant(vx, N), ty = variant(vy, N);
+    const T* qx = sQ + tx * NN;
     const T* qy = sQ + ty * NN;
-    T col[n], t[n];
-#pragma unroll
-    for (int a = 0; a < n; ++a) col[a] = sA[p * NN + a * n + c];
-#pragma unroll
-    for (int ap = 0; ap < n; ++ap) {
+    T* pA = sA + p * NN;
+    T* pB = sB + p * NN;
+    if (on) {
       T s = 0;
 #pragma unroll
-      for (int a = 0; a < n; ++a) s += qy[a * n + ap] * col[a];
-      t[ap] = s / (sLam[tx * n + c] + sLam[ty * n + ap]);
+      for (int j = 0; j < n; ++j) s += qx[j * n + c] * pB[a * n + j];
+      pA[a * n + c] = s;
     }
-#pragma unroll
-    for (int a = 0; a < n; ++a) {
+    __syncthreads();
+    if (on) {
       T s = 0;
 #pragma unroll
-      for (int ap = 0; ap < n; ++ap) s += qy[a * n + ap] * t[ap];
-      sB[p * NN + a * n + c] = s;
+      for (int j = 0; j < n; ++j) s += qy[j * n + a] * pA[j * n + c];
+      pB[a * n + c] = s / (sLam[tx * n + c] + sLam[ty * n + a]);
     }
-  }
-  __syncthreads();
-  // back along x into sA, then x += omega u on the patches' nodes
-  for (int it = threadIdx.x; it < np * n; it += kThreads) {
-    const int p = it / n, a = it - p * n;
-    int vx, vy;
-    colour_vertex(cr, px, py, q0 + p, vx, vy);
-    const T* qx = sQ + variant(vx, N) * NN;
-    T in[n];
-#pragma unroll
-    for (int c = 0; c < n; ++c) in[c] = sB[p * NN + a * n + c];
-#pragma unroll
-    for (int cp = 0; cp < n; ++cp) {
+    __syncthreads();
+    if (on) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < n; ++c) s += qx[cp * n + c] * in[c];
-      sA[p * NN + a * n + cp] = s;
+      for (int j = 0; j < n; ++j) s += qy[a * n + j] * pB[j * n + c];
+      pA[a * n + c] = s;
+    }
+    __syncthreads();
+    if (on) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < n; ++j) s += qx[c * n + j] * pA[a * n + j];
+      pB[a * n + c] = s;
     }
   }
   __syncthreads();
+  // x += omega u on the patches' nodes
+  const T* u = EXACT ? sA : sB;
   for (int e = threadIdx.x; e < np * NN; e += kThreads) {
     const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
     int vx, vy;
     colour_vertex(cr, px, py, q0 + p, vx, vy);
     const size_t g = (size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c;
-    x[g] = x[g] + omega * sA[e];
+    x[g] = x[g] + omega * u[e];
   }
 }
 
-template <typename T, int K>
-hipError_t mvs2d_colour_k(int N, int colour, const LevelEig<T>& e, const T* r, T* x, T omega, hipStream_t s) {
-  constexpr int NPW = ColourPatches<K>::NPW;
+template <typename T, int K, bool EXACT>
+hipError_t mvs2d_colour_k(int N, int colour, const LevelCoef<T>& cf, const T* Q, const T* lam, const T* Aex,
+                          const T* b, const T* r, T* x, T omega, hipStream_t s) {
+  constexpr int NP = ColourFused<K>::NP;
   const ColourRows cr = colour_rows(N, colour);
   if (cr.total <= 0) return hipSuccess;
-  const int nblk = (cr.total + NPW - 1) / NPW;
-  mvs2d_colour_kernel<T, K, false><<<nblk, kThreads, 0, s>>>(r, x, N, K * N + 1, cr, colour & 1, (colour >> 1) & 1,
-                                                            e.Q, e.lam, nullptr, omega);
-  return hipGetLastError();
-}
-
-template <typename T, int K>
-hipError_t mvs2d_colour_exact_k(int N, int colour, const T* Aex, const T* r, T* x, T omega, hipStream_t s) {
-  constexpr int NPW = ColourPatches<K>::NPW;
-  const ColourRows cr = colour_rows(N, colour);
-  if (cr.total <= 0) return hipSuccess;
-  const int nblk = (cr.total + NPW - 1) / NPW;
-  mvs2d_colour_kernel<T, K, true><<<nblk, kThreads, 0, s>>>(r, x, N, K * N + 1, cr, colour & 1, (colour >> 1) & 1,
-                                                           nullptr, nullptr, Aex, omega);
+  if (cf.nclass > ColourFused<K>::MAXCLASS) return hipErrorInvalidValue;
+  const int nblk = (cr.total + NP - 1) / NP;
+  mvs2d_colour_kernel<T, K, EXACT><<<nblk, kThreads, 0, s>>>(b, x, N, K * N + 1, cr, colour & 1, (colour >> 1) & 1,
+                                                            cf.tab, cf.nclass, cf.left, cf.right0, cf.periodic,
+                                                            r, Q, lam, Aex, omega);
   return hipGetLastError();
 }
 
@@ -748,9 +804,9 @@ hipError_t launch_patch2d_atomic(int k, int N, const LevelEig<T>& e, const T* r,
 }
 
 template <typename T>
-hipError_t launch_mvs2d_colour(int k, int N, int colour, const LevelEig<T>& e, const T* r, T* x, T omega,
-                               hipStream_t s) {
-#define CALL(K) mvs2d_colour_k<T, K>(N, colour, e, r, x, omega, s)
+hipError_t launch_mvs2d_colour(int k, int N, int colour, const LevelCoef<T>& c, const LevelEig<T>& e, const T* b,
+                               const T* r, T* x, T omega, hipStream_t s) {
+#define CALL(K) mvs2d_colour_k<T, K, false>(N, colour, c, e.Q, e.lam, nullptr, b, r, x, omega, s)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
@@ -764,9 +820,9 @@ hipError_t launch_patch2d_exact(int k, int N, const T* Aex, const T* r, const T*
 }
 
 template <typename T>
-hipError_t launch_mvs2d_colour_exact(int k, int N, int colour, const T* Aex, const T* r, T* x, T omega,
-                                     hipStream_t s) {
-#define CALL(K) mvs2d_colour_exact_k<T, K>(N, colour, Aex, r, x, omega, s)
+hipError_t launch_mvs2d_colour_exact(int k, int N, int colour, const LevelCoef<T>& c, const T* Aex, const T* b,
+                                     const T* r, T* x, T omega, hipStream_t s) {
+#define CALL(K) mvs2d_colour_k<T, K, true>(N, colour, c, nullptr, nullptr, Aex, b, r, x, omega, s)
   C0IP_DISPATCH_K(k, CALL)
 #undef CALL
 }
@@ -799,18 +855,18 @@ template hipError_t launch_patch2d_atomic<double>(int, int, const LevelEig<doubl
                                                   double, hipStream_t);
 template hipError_t launch_patch2d_atomic<float>(int, int, const LevelEig<float>&, const float*, float*, float,
                                                  hipStream_t);
-template hipError_t launch_mvs2d_colour<double>(int, int, int, const LevelEig<double>&, const double*, double*,
-                                                double, hipStream_t);
-template hipError_t launch_mvs2d_colour<float>(int, int, int, const LevelEig<float>&, const float*, float*, float,
-                                               hipStream_t);
+template hipError_t launch_mvs2d_colour<double>(int, int, int, const LevelCoef<double>&, const LevelEig<double>&,
+                                                const double*, const double*, double*, double, hipStream_t);
+template hipError_t launch_mvs2d_colour<float>(int, int, int, const LevelCoef<float>&, const LevelEig<float>&,
+                                                const float*, const float*, float*, float, hipStream_t);
 template hipError_t launch_patch2d_exact<double>(int, int, const double*, const double*, const double*, double*,
                                                  double, hipStream_t);
 template hipError_t launch_patch2d_exact<float>(int, int, const float*, const float*, const float*, float*, float,
                                                 hipStream_t);
-template hipError_t launch_mvs2d_colour_exact<double>(int, int, int, const double*, const double*, double*, double,
-                                                      hipStream_t);
-template hipError_t launch_mvs2d_colour_exact<float>(int, int, int, const float*, const float*, float*, float,
-                                                     hipStream_t);
+template hipError_t launch_mvs2d_colour_exact<double>(int, int, int, const LevelCoef<double>&, const double*,
+                                                      const double*, const double*, double*, double, hipStream_t);
+template hipError_t launch_mvs2d_colour_exact<float>(int, int, int, const LevelCoef<float>&, const float*,
+                                                      const float*, const float*, float*, float, hipStream_t);
 template hipError_t launch_patch2d<double>(int, int, const LevelEig<double>&, const double*, const double*,
                                            double*, double, hipStream_t, int, int64_t, const int*);
 template hipError_t launch_patch2d<float>(int, int, const LevelEig<float>&, const float*, const float*, float*,

@@ -3,7 +3,9 @@ Sec. 3 and Fig. 2: 8 colours in 2D, a residual per colour) against the
 oracle's coloured sweep (itself pinned to the one-patch-at-a-time
 definition on the CPU): smoother steps in both precisions, the V-cycle
 with MVS, and the MVS-preconditioned FGMRES solve, in 2D (8 colours) and
-3D (16 colours).  Bars in
+3D (16 colours); in 2D the two places a colour's residual can be formed
+(in the colour's launch, or a full residual pass) agree bit for bit, also
+on a mesh above the automatic switch between them.  Bars in
 tests/gpu_util.py."""
 import numpy as np
 import pytest
@@ -105,10 +107,69 @@ def test_mvs_solve(dim, k, N, omega):
     assert pa.solve(dev(b), xa)["iterations"] > its[P.C0IP_F64]
 
 
+def _mvs_outputs(dim, k, N, mode, x, b, tdt, local_solver=0):
+    """S(x, b), S(0, b) and a V-cycle of b with the given mvs_residual mode."""
+    pb = P.Problem(dim, N, k, omega=1.0, smoother=1, local_solver=local_solver, mvs_residual=mode,
+                   vcycle_dtype=P.C0IP_F32 if tdt == torch.float32 else P.C0IP_F64)
+    xs = x.clone()
+    pb.apply_smoother(b, xs)
+    x0 = torch.empty_like(x)
+    pb.smoother_step(b, None, x0)
+    z = torch.empty_like(x)
+    pb.vcycle(b, z)
+    torch.cuda.synchronize()
+    pb.close()
+    return [t.cpu() for t in (xs, x0, z)]
+
+
+@pytest.mark.parametrize("k,N,local_solver", [(2, 16, 0), (3, 32, 0), (4, 8, 0), (5, 8, 0), (7, 4, 0), (2, 2, 0),
+                                              (3, 16, 1), (5, 4, 1), (7, 4, 1)])
+@pytest.mark.parametrize("tdt", [torch.float64, torch.float32])
+def test_mvs_residual_modes_agree_bitwise(k, N, local_solver, tdt):
+    """2D: each colour's residual formed in the colour's launch (mode 1) or
+    by a full residual pass (mode 2), and the automatic choice (mode 0),
+    give the same S(x, b), S(0, b) and V-cycle bit for bit (the same sums
+    in the same order); mode 1 is the one the oracle tests above check at
+    these sizes."""
+    say("mvs residual modes", k, N, local_solver, tdt)
+    x, b = vectors(2, k, N)
+    xd, bd = dev(x, tdt), dev(b, tdt)
+    outs = [_mvs_outputs(2, k, N, m, xd, bd, tdt, local_solver) for m in (0, 1, 2)]
+    for m in (1, 2):
+        for name, u, v in zip(("S(x,b)", "S(0,b)", "V-cycle"), outs[0], outs[m]):
+            assert torch.equal(u, v), (m, name, float((u - v).abs().max()))
+
+
+@pytest.mark.timeout(300)
+def test_mvs_residual_modes_above_the_switch():
+    """2D Q2 512^2 (1,050,625 DoFs, above the 2^20 switch): the automatic
+    mode uses the full residual pass on the finest level and the in-launch
+    residual below; both fixed modes give the same results bit for bit,
+    in both precisions."""
+    dim, k, N = 2, 2, 512
+    assert (k * N + 1) ** 2 >= 2 ** 20 > (k * N // 2 + 1) ** 2
+    say("mvs residual modes above the switch", dim, k, N)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(77)
+    n = (k * N + 1) ** 2
+    x = torch.rand(n, generator=g, dtype=torch.float64, device="cuda") * 2 - 1
+    b = torch.rand(n, generator=g, dtype=torch.float64, device="cuda") * 2 - 1
+    for tdt in (torch.float64, torch.float32):
+        outs = [_mvs_outputs(dim, k, N, m, x.to(tdt), b.to(tdt), tdt) for m in (0, 1, 2)]
+        for m in (1, 2):
+            for name, u, v in zip(("S(x,b)", "S(0,b)", "V-cycle"), outs[0], outs[m]):
+                assert torch.equal(u, v), (tdt, m, name, float((u - v).abs().max()))
+        assert bool(torch.isfinite(outs[0][2]).all())
+
+
 def test_mvs_options_rejected():
     with pytest.raises(P.C0ipError) as e:
         P.Problem(2, 8, 2, smoother=1, scatter_mode=1)
     assert e.value.status == -1
+    for mode in (-1, 3):
+        with pytest.raises(P.C0ipError) as e:
+            P.Problem(2, 8, 2, smoother=1, mvs_residual=mode)
+        assert e.value.status == -1
     with pytest.raises(P.C0ipError) as e:
         P.Problem(2, 8, 2, smoother=2)
     assert e.value.status == -1
