@@ -317,7 +317,7 @@ void c0ip_problem::smooth_mvs(int l, const T* b, T* x, T* r, int steps, bool x_i
   // mvs_residual 0 (automatic): on 2D levels under 2^20 DoFs one launch per colour forms the residual on
   // the colour's patch rows (it halves the launches, which bound these levels); on finer levels a full
   // residual pass with the tiled operator precedes the colour's solves (there the operator's efficiency
-  // wins: Q3 512^2 310 against 452 us per float64 step, 256^2 184 against 168 us)
+  // wins: Q3 512^2 315 against 357 us per float64 step; 256^2 183 against 146 us)
   for (int s = 0; s < steps; ++s)
     for (int c = 0; c < ncol; ++c) {
       const bool zero = s == 0 && c == 0 && x_is_zero;

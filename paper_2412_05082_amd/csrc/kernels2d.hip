@@ -450,16 +450,60 @@ struct ColourFused {
   static constexpr int n = 2 * K - 1, NN = n * n, C = 2 * K + 1, W = 4 * K + 1, R = C * W;
   static constexpr int NP = kThreads / NN > 0 ? kThreads / NN : 1;
   static constexpr int MAXCLASS = 5 * K + 2, TAB = 3 * MAXCLASS * W;
+  static_assert(NP * NN <= kThreads, "one node per thread in the y passes and the update");
 };
 
-// Band product of factor OP for a row of class cl at cell position p (sTab:
-// the table in LDS); v points at the row's own tap, taps `stride` apart.
-template <typename T, int OP, int K>
-__device__ __forceinline__ T colour_band(const T* sTab, int nclass, int cl, int p, const T* v, int stride) {
-  const T* c = sTab + (OP * nclass + cl) * (4 * K + 1) + 2 * K;
+// Band products for a row at cell position P (compile time), taps `stride`
+// apart from the row's own tap v[0]; c: the row's coefficients, centred.
+// Each accumulates its taps from the band's low end up, as the tiled
+// operator does.
+template <typename T, int OP, int K, int P>
+__device__ __forceinline__ T band_fixed(const T* c, const T* v, int stride) {
   T a = 0;
-  for (int o = tile::Band<OP, K>::lo(p); o <= tile::Band<OP, K>::hi(p); ++o) a += c[o] * v[o * stride];
+#pragma unroll
+  for (int o = tile::Band<OP, K>::lo(P); o <= tile::Band<OP, K>::hi(P); ++o) a += c[o] * v[o * stride];
   return a;
+}
+
+// OP at the row's cell position p (a runtime value, nearly uniform over a wave).
+template <typename T, int OP, int K, int P = 0>
+__device__ __forceinline__ T band_at(const T* c, int p, const T* v, int stride) {
+  if constexpr (P + 1 < K) {
+    if (p != P) return band_at<T, OP, K, P + 1>(c, p, v, stride);
+  }
+  return band_fixed<T, OP, K, P>(c, v, stride);
+}
+
+// B and L of one row over the same taps (B's band contains L's), sharing the loads.
+template <typename T, int K, int P>
+__device__ __forceinline__ void band_bl_fixed(const T* cB, const T* cL, const T* v, T& aB, T& aL) {
+  using BB = tile::Band<2, K>;
+  using BL = tile::Band<1, K>;
+  aB = 0;
+  aL = 0;
+#pragma unroll
+  for (int o = BB::lo(P); o <= BB::hi(P); ++o) {
+    const T w = v[o];
+    aB += cB[o] * w;
+    if (o >= BL::lo(P) && o <= BL::hi(P)) aL += cL[o] * w;
+  }
+}
+
+template <typename T, int K, int P = 0>
+__device__ __forceinline__ void band_bl_at(const T* cB, const T* cL, int p, const T* v, T& aB, T& aL) {
+  if constexpr (P + 1 < K) {
+    if (p != P) {
+      band_bl_at<T, K, P + 1>(cB, cL, p, v, aB, aL);
+      return;
+    }
+  }
+  band_bl_fixed<T, K, P>(cB, cL, v, aB, aL);
+}
+
+// Row cl of factor OP in the LDS table, centred on its own tap.
+template <typename T, int OP, int K>
+__device__ __forceinline__ const T* table_row(const T* sTab, int nclass, int cl) {
+  return sTab + (OP * nclass + cl) * (4 * K + 1) + 2 * K;
 }
 
 // x <- x + omega * sum over the colour's patches of R_v^T A~_v^{-1} R_v r
@@ -488,31 +532,60 @@ __global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restr
   const int q0 = blockIdx.x * NP;
   const int np = min(NP, cr.total - q0);
   if (np <= 0) return;
+  // This thread's node of the y passes and the update (at most one: NP (2K-1)^2 <= kThreads; rows
+  // slowest).  Its b (or r) and x are loaded first, so that their latency overlaps the staging.
+  const bool mine = threadIdx.x < np * NN;
+  int ya = 0, yp = 0, yc = 0, vxm = 1, vym = 1;
+  if (mine) {
+    ya = threadIdx.x / (np * n);
+    const int rem = threadIdx.x - ya * (np * n);
+    yp = rem / n;
+    yc = rem - yp * n;
+    colour_vertex(cr, px, py, q0 + yp, vxm, vym);
+  }
+  const size_t gm = (size_t)((vym - 1) * K + 1 + ya) * n1 + (vxm - 1) * K + 1 + yc;
+  const T bm = mine ? (rsrc ? rsrc[gm] : b[gm]) : T(0);
+  const T xm = mine ? x[gm] : T(0);
   if (rsrc) {
-    for (int e = threadIdx.x; e < np * NN; e += kThreads) {
-      const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
-      int vx, vy;
-      colour_vertex(cr, px, py, q0 + p, vx, vy);
-      sB[e] = rsrc[(size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c];
-    }
+    if (mine) sB[yp * NN + ya * n + yc] = bm;
   } else {
-    // stage the two strips of x (zero outside the mesh) and the table
-    for (int e = threadIdx.x; e < np * R; e += kThreads) {
-      const int p = e / R, loc = e - p * R;
-      int vx, vy;
-      colour_vertex(cr, px, py, q0 + p, vx, vy);
-      {
+    // stage the two strips of x (zero outside the mesh) and the table, every load issued before the stores
+    constexpr int NS = (NP * R + kThreads - 1) / kThreads, NT = (F::TAB + kThreads - 1) / kThreads;
+    T vr[NS], vc[NS], vt[NT];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      vr[u] = vc[u] = T(0);
+      if (e < np * R) {
+        const int p = e / R, loc = e - p * R;
+        int vx, vy;
+        colour_vertex(cr, px, py, q0 + p, vx, vy);
         const int i = loc / W, j = loc - i * W;
         const int gy = (vy - 1) * K + i, gx = (vx - 2) * K + j;
-        sRow[e] = (gx >= 0 && gx < n1) ? x[(size_t)gy * n1 + gx] : T(0);
-      }
-      {
-        const int i = loc / C, j = loc - i * C;
-        const int gy = (vy - 2) * K + i, gx = (vx - 1) * K + j;
-        sCol[e] = (gy >= 0 && gy < n1) ? x[(size_t)gy * n1 + gx] : T(0);
+        if (gx >= 0 && gx < n1) vr[u] = x[(size_t)gy * n1 + gx];
+        const int i2 = loc / C, j2 = loc - i2 * C;
+        const int gy2 = (vy - 2) * K + i2, gx2 = (vx - 1) * K + j2;
+        if (gy2 >= 0 && gy2 < n1) vc[u] = x[(size_t)gy2 * n1 + gx2];
       }
     }
-    for (int e = threadIdx.x; e < 3 * nclass * W; e += kThreads) sTab[e] = tab[e];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      vt[u] = e < 3 * nclass * W ? tab[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < np * R) {
+        sRow[e] = vr[u];
+        sCol[e] = vc[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < 3 * nclass * W) sTab[e] = vt[u];
+    }
     __syncthreads();
     // x passes at the patch's interior columns: X B_x and X L_x on the patch
     // rows, X M_x on 4K+1 rows (items ordered column-major, so that the
@@ -524,26 +597,28 @@ __global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restr
       const int gx = (vx - 1) * K + 1 + c, pc = (1 + c) % K;
       const int cl = tile::row_class(gx, n1, K, left, right0, periodic);
       if (i < C) {
-        const T* v = sRow + p * R + i * W + K + 1 + c;
-        sTB[(p * C + i) * n + c] = colour_band<T, 2, K>(sTab, nclass, cl, pc, v, 1);
-        sTL[(p * C + i) * n + c] = colour_band<T, 1, K>(sTab, nclass, cl, pc, v, 1);
+        T aB, aL;
+        band_bl_at<T, K>(table_row<T, 2, K>(sTab, nclass, cl), table_row<T, 1, K>(sTab, nclass, cl), pc,
+                         sRow + p * R + i * W + K + 1 + c, aB, aL);
+        sTB[(p * C + i) * n + c] = aB;
+        sTL[(p * C + i) * n + c] = aL;
       } else {
         const int iw = i - C;
-        sTM[(p * W + iw) * n + c] = colour_band<T, 0, K>(sTab, nclass, cl, pc, sCol + p * R + iw * C + 1 + c, 1);
+        sTM[(p * W + iw) * n + c] =
+            band_at<T, 0, K>(table_row<T, 0, K>(sTab, nclass, cl), pc, sCol + p * R + iw * C + 1 + c, 1);
       }
     }
     __syncthreads();
-    // y passes: r = b - (M_y TB + 2 L_y TL + B_y TM) at the patch's interior rows (row-major items)
-    for (int e = threadIdx.x; e < np * NN; e += kThreads) {
-      const int a = e / (np * n), rem = e - a * (np * n), p = rem / n, c = rem - p * n;
-      int vx, vy;
-      colour_vertex(cr, px, py, q0 + p, vx, vy);
-      const int gy = (vy - 1) * K + 1 + a, pa = (1 + a) % K;
+    // y passes: r = b - (M_y TB + 2 L_y TL + B_y TM) at this thread's node
+    if (mine) {
+      const int gy = (vym - 1) * K + 1 + ya, pa = (1 + ya) % K;
       const int cl = tile::row_class(gy, n1, K, left, right0, periodic);
-      const T ax = colour_band<T, 0, K>(sTab, nclass, cl, pa, sTB + (p * C + 1 + a) * n + c, n) +
-                   T(2) * colour_band<T, 1, K>(sTab, nclass, cl, pa, sTL + (p * C + 1 + a) * n + c, n) +
-                   colour_band<T, 2, K>(sTab, nclass, cl, pa, sTM + (p * W + K + 1 + a) * n + c, n);
-      sB[p * NN + a * n + c] = b[(size_t)gy * n1 + (vx - 1) * K + 1 + c] - ax;
+      const T ax = band_at<T, 0, K>(table_row<T, 0, K>(sTab, nclass, cl), pa, sTB + (yp * C + 1 + ya) * n + yc, n) +
+                   T(2) * band_at<T, 1, K>(table_row<T, 1, K>(sTab, nclass, cl), pa,
+                                           sTL + (yp * C + 1 + ya) * n + yc, n) +
+                   band_at<T, 2, K>(table_row<T, 2, K>(sTab, nclass, cl), pa, sTM + (yp * W + K + 1 + ya) * n + yc,
+                                    n);
+      sB[yp * NN + ya * n + yc] = bm - ax;
     }
   }
   if constexpr (EXACT) {
@@ -605,15 +680,9 @@ __global__ __launch_bounds__(kThreads) void mvs2d_colour_kernel(const T* __restr
     }
   }
   __syncthreads();
-  // x += omega u on the patches' nodes
+  // x += omega u at this thread's node (no other workgroup of the launch reads or writes it)
   const T* u = EXACT ? sA : sB;
-  for (int e = threadIdx.x; e < np * NN; e += kThreads) {
-    const int p = e / NN, loc = e - p * NN, a = loc / n, c = loc - a * n;
-    int vx, vy;
-    colour_vertex(cr, px, py, q0 + p, vx, vy);
-    const size_t g = (size_t)((vy - 1) * K + 1 + a) * n1 + (vx - 1) * K + 1 + c;
-    x[g] = x[g] + omega * u[e];
-  }
+  if (mine) x[gm] = xm + omega * u[yp * NN + ya * n + yc];
 }
 
 template <typename T, int K, bool EXACT>

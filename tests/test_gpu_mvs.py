@@ -3,18 +3,17 @@ Sec. 3 and Fig. 2: 8 colours in 2D, a residual per colour) against the
 oracle's coloured sweep (itself pinned to the one-patch-at-a-time
 definition on the CPU): smoother steps in both precisions, the V-cycle
 with MVS, and the MVS-preconditioned FGMRES solve, in 2D (8 colours) and
-3D (16 colours); in 2D the two places a colour's residual can be formed
-(in the colour's launch, or a full residual pass) agree bit for bit, also
-on a mesh above the automatic switch between them.  Bars in
-tests/gpu_util.py."""
+3D (16 colours); in 2D both places a colour's residual can be formed (in
+the colour's launch, or a full residual pass) are checked, also on a mesh
+above the automatic switch between them.  Bars in tests/gpu_util.py."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
 import paper_2412_05082_amd as P
-from tests.gpu_util import (check, dev, fp32_mvs_tol, fp32_vcycle_tol, fp64_mvs_tol, fp64_vcycle_tol, host,
-                            mvs_ops, rel_l2, say, vectors)
+from tests.gpu_util import (check, dev, exact_ops, fp32_exact_floor, fp32_mvs_tol, fp32_vcycle_tol, fp64_exact_tol,
+                            fp64_mvs_tol, fp64_vcycle_tol, host, mvs_ops, rel_l2, say, vectors)
 
 pytestmark = pytest.mark.gpu
 
@@ -119,33 +118,58 @@ def _mvs_outputs(dim, k, N, mode, x, b, tdt, local_solver=0):
     pb.vcycle(b, z)
     torch.cuda.synchronize()
     pb.close()
-    return [t.cpu() for t in (xs, x0, z)]
+    return [t.cpu().double().numpy() for t in (xs, x0, z)]
+
+
+def _mode_bars(k, N, tdt, local_solver=0):
+    """Bars for S(x,b), S(0,b) and the V-cycle: the oracle bars of the tests above."""
+    if local_solver == 1:  # one exact-solver bar per colour sub-step, as fp64_mvs_tol does for the separable one
+        one = fp64_exact_tol(2, k, N) if tdt == torch.float64 else max(1e-5, 2 * fp32_exact_floor(2, k, N, 1.0))
+        return 8 * one, 8 * one, None
+    if tdt == torch.float64:
+        return fp64_mvs_tol(2, k, N), fp64_mvs_tol(2, k, N), 8 * fp64_vcycle_tol(2, k, N)
+    return (fp32_mvs_tol(2, k, N, 1.0), fp32_mvs_tol(2, k, N, 1.0),
+            fp32_vcycle_tol(2, k, N, 1.0, smoother="mvs"))
 
 
 @pytest.mark.parametrize("k,N,local_solver", [(2, 16, 0), (3, 32, 0), (4, 8, 0), (5, 8, 0), (7, 4, 0), (2, 2, 0),
                                               (3, 16, 1), (5, 4, 1), (7, 4, 1)])
 @pytest.mark.parametrize("tdt", [torch.float64, torch.float32])
-def test_mvs_residual_modes_agree_bitwise(k, N, local_solver, tdt):
-    """2D: each colour's residual formed in the colour's launch (mode 1) or
-    by a full residual pass (mode 2), and the automatic choice (mode 0),
-    give the same S(x, b), S(0, b) and V-cycle bit for bit (the same sums
-    in the same order); mode 1 is the one the oracle tests above check at
-    these sizes."""
+def test_mvs_residual_modes_match_oracle(k, N, local_solver, tdt):
+    """2D: each colour's residual formed in the colour's launch (mode 1), by
+    a full residual pass (mode 2), or by the automatic choice (mode 0, which
+    is mode 1 at these sizes): S(x, b), S(0, b) and the V-cycle of each mode
+    against the oracle, at the bars of the tests above."""
     say("mvs residual modes", k, N, local_solver, tdt)
+    if local_solver == 1:
+        A, blocks, pidx, _ = exact_ops(2, k, N)
+        col = O.mvs_colors(2, N)
+    else:
+        A, blocks, pidx, col = mvs_ops(2, k, N)
     x, b = vectors(2, k, N)
-    xd, bd = dev(x, tdt), dev(b, tdt)
-    outs = [_mvs_outputs(2, k, N, m, xd, bd, tdt, local_solver) for m in (0, 1, 2)]
-    for m in (1, 2):
-        for name, u, v in zip(("S(x,b)", "S(0,b)", "V-cycle"), outs[0], outs[m]):
-            assert torch.equal(u, v), (m, name, float((u - v).abs().max()))
+    if tdt == torch.float32:
+        x, b = x.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
+    ref = O.mvs_apply(A, blocks, pidx, col, x, b, 1.0)
+    ref0 = O.mvs_apply(A, blocks, pidx, col, None, b, 1.0, x_is_zero=True)
+    refz = None
+    if local_solver == 0:
+        refz = O.Hierarchy(2, k, N, omega=1.0, smoother="mvs").vcycle(b)
+    bars = _mode_bars(k, N, tdt, local_solver)
+    for m in (0, 1, 2):
+        xs, x0, z = _mvs_outputs(2, k, N, m, dev(x, tdt), dev(b, tdt), tdt, local_solver)
+        check(f"mode {m} S(x,b)", rel_l2(xs, ref), bars[0])
+        check(f"mode {m} S(0,b)", rel_l2(x0, ref0), bars[1])
+        if refz is not None:
+            check(f"mode {m} V-cycle", rel_l2(z, refz), bars[2])
 
 
 @pytest.mark.timeout(300)
 def test_mvs_residual_modes_above_the_switch():
     """2D Q2 512^2 (1,050,625 DoFs, above the 2^20 switch): the automatic
     mode uses the full residual pass on the finest level and the in-launch
-    residual below; both fixed modes give the same results bit for bit,
-    in both precisions."""
+    residual below; the two fixed modes agree with it to the oracle bars of
+    the tests above (taken on 64^2, the oracle's floors depend on k, hardly
+    on N), in both precisions."""
     dim, k, N = 2, 2, 512
     assert (k * N + 1) ** 2 >= 2 ** 20 > (k * N // 2 + 1) ** 2
     say("mvs residual modes above the switch", dim, k, N)
@@ -155,11 +179,12 @@ def test_mvs_residual_modes_above_the_switch():
     x = torch.rand(n, generator=g, dtype=torch.float64, device="cuda") * 2 - 1
     b = torch.rand(n, generator=g, dtype=torch.float64, device="cuda") * 2 - 1
     for tdt in (torch.float64, torch.float32):
+        bars = _mode_bars(k, 64, tdt)
         outs = [_mvs_outputs(dim, k, N, m, x.to(tdt), b.to(tdt), tdt) for m in (0, 1, 2)]
         for m in (1, 2):
-            for name, u, v in zip(("S(x,b)", "S(0,b)", "V-cycle"), outs[0], outs[m]):
-                assert torch.equal(u, v), (tdt, m, name, float((u - v).abs().max()))
-        assert bool(torch.isfinite(outs[0][2]).all())
+            for name, u, v, bar in zip(("S(x,b)", "S(0,b)", "V-cycle"), outs[0], outs[m], bars):
+                check(f"{tdt} mode 0 vs {m} {name}", rel_l2(v, u), bar)
+        assert np.isfinite(outs[0][2]).all()
 
 
 def test_mvs_options_rejected():
