@@ -56,9 +56,7 @@ __global__ __launch_bounds__(kThreads) void patch2d_kernel(const T* __restrict__
       const int gy = oy + rr, gx = ox + cc;
       v[q] = (e < S * S && gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2) ? r[(size_t)gy * n1 + gx] : T(0);
     }
-    for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
-    for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
-    for (int e = threadIdx.x; e < NN; e += kThreads) sD[e] = T(1) / (lamg[e % n] + lamg[e / n]);  // [ap][c]
+    tile::stage_eig<T, n, kThreads>(Qg, lamg, sQ, sLam, sD);
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       const int e = threadIdx.x + q * kThreads;

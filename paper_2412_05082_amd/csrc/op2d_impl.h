@@ -32,6 +32,7 @@ namespace {
 using tile::Band;
 using tile::band_row;
 using tile::clampi;
+using tile::stage_eig;
 
 // Cell positions [p0, end) whose bands of factor OP fit the scalar budget
 // (80 SGPRs of coefficients).
@@ -163,11 +164,26 @@ __device__ __forceinline__ bool tile_yin(int periodic, int left, int right0, int
 }
 
 // Copy the coefficient table to LDS on tiles that need per-lane classes.
+// Here and in the other staging helpers every global load of a thread is
+// issued before its first LDS store, so that the loads' latencies overlap.
 template <typename T, class G>
 __device__ __forceinline__ void stage_tab(const T* __restrict__ tab, T* __restrict__ sTab, int nclass, bool need) {
   if (!need) return;
-  for (int e = threadIdx.x; e < 3 * nclass * G::W; e += G::NTH) sTab[e] = tab[e];
+  constexpr int NL = (G::TABMAX + G::NTH - 1) / G::NTH;
+  const int cnt = 3 * nclass * G::W;
+  T v[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = threadIdx.x + q * G::NTH;
+    v[q] = e < cnt ? tab[e] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = threadIdx.x + q * G::NTH;
+    if (e < cnt) sTab[e] = v[q];
+  }
 }
+
 
 template <typename T, class G>
 __device__ __forceinline__ void op_tile_any(const T* __restrict__ sX, T* __restrict__ sT,
@@ -433,12 +449,32 @@ __device__ __forceinline__ void prolong_into(T* __restrict__ sX, T* __restrict__
   const int nc = (nf - 1) / 2 + 1;
   const int f0x = x0 - G::H, f0y = y0 - G::H;
   const int cxl = ((f0x > 0 ? f0x : 0) / K >> 1) * K, cyl = ((f0y > 0 ? f0y : 0) / K >> 1) * K;
-  for (int e = threadIdx.x; e < CX * CX; e += NTH) {
-    const int r = e / CX, c = e - r * CX;
-    const int gy = cyl + r, gx = cxl + c;
-    sC[e] = (gy < nc && gx < nc) ? ec[(size_t)gy * nc + gx] : T(0);
+  {
+    constexpr int NLC = (CX * CX + NTH - 1) / NTH, NLT = (NT + NTH - 1) / NTH;
+    T v[NLC], t[NLT];
+#pragma unroll
+    for (int q = 0; q < NLC; ++q) {
+      const int e = threadIdx.x + q * NTH;
+      const int r = e / CX, c = e - r * CX;
+      const int gy = cyl + r, gx = cxl + c;
+      v[q] = (e < CX * CX && gy < nc && gx < nc) ? ec[(size_t)gy * nc + gx] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NLT; ++q) {
+      const int e = threadIdx.x + q * NTH;
+      t[q] = e < NT ? ptab[e] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NLC; ++q) {
+      const int e = threadIdx.x + q * NTH;
+      if (e < CX * CX) sC[e] = v[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NLT; ++q) {
+      const int e = threadIdx.x + q * NTH;
+      if (e < NT) sPT[e] = t[q];
+    }
   }
-  for (int e = threadIdx.x; e < NT; e += NTH) sPT[e] = ptab[e];
   __syncthreads();
   for (int e = threadIdx.x; e < CX * RX; e += NTH) {
     const int r = e / RX, c = e - r * RX;
@@ -501,9 +537,7 @@ __global__ __launch_bounds__(S::NTH) void avs2d_kernel(const T* __restrict__ x, 
   stage_x<T, T, G>(x, sX, x0, y0, n1);
   stage_tab<T, G>(tab, sTab, nclass,
                   !(tile_xin<G>(periodic, left, right0, x0) && tile_yin<G>(periodic, left, right0, y0)));
-  for (int e = threadIdx.x; e < 4 * NN; e += NTH) sQ[e] = Qg[e];
-  for (int e = threadIdx.x; e < 4 * n; e += NTH) sLam[e] = lamg[e];
-  for (int e = threadIdx.x; e < NN; e += NTH) sD[e] = T(1) / (lamg[e % n] + lamg[e / n]);  // [ap][c]
+  stage_eig<T, n, NTH>(Qg, lamg, sQ, sLam, sD);
   // b on the residual tile, loaded now so that its latency overlaps the passes
   T bv[G::NI][G::RW * K];
 #pragma unroll
@@ -631,14 +665,23 @@ __global__ __launch_bounds__(S::NTH) void pre2d_kernel(const T* __restrict__ b, 
   const int x0 = cx0 * K, y0 = cy0 * K;  // operator tile origin (owned nodes)
   const int bx0 = (cx0 - 3) * K + 1, by0 = (cy0 - 3) * K + 1;  // staged b origin
   // b on the staged region (0 outside the interior nodes)
-  for (int e = threadIdx.x; e < SB * SB; e += NTH) {
-    const int rr = e / SB, cc = e - rr * SB;
-    const int gy = by0 + rr, gx = bx0 + cc;
-    regA[e] = (gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2) ? b[(size_t)gy * n1 + gx] : T(0);
+  {
+    constexpr int NLB = (SB * SB + NTH - 1) / NTH;
+    T v[NLB];
+#pragma unroll
+    for (int q = 0; q < NLB; ++q) {
+      const int e = threadIdx.x + q * NTH;
+      const int rr = e / SB, cc = e - rr * SB;
+      const int gy = by0 + rr, gx = bx0 + cc;
+      v[q] = (e < SB * SB && gx >= 1 && gx <= n1 - 2 && gy >= 1 && gy <= n1 - 2) ? b[(size_t)gy * n1 + gx] : T(0);
+    }
+    stage_eig<T, n, NTH>(Qg, lamg, sQ, sLam, sD);
+#pragma unroll
+    for (int q = 0; q < NLB; ++q) {
+      const int e = threadIdx.x + q * NTH;
+      if (e < SB * SB) regA[e] = v[q];
+    }
   }
-  for (int e = threadIdx.x; e < 4 * NN; e += NTH) sQ[e] = Qg[e];
-  for (int e = threadIdx.x; e < 4 * n; e += NTH) sLam[e] = lamg[e];
-  for (int e = threadIdx.x; e < NN; e += NTH) sD[e] = T(1) / (lamg[e % n] + lamg[e / n]);  // [ap][c]
   stage_tab<T, G>(tab, sTab, nclass,
                   !(tile_xin<G>(periodic, left, right0, x0) && tile_yin<G>(periodic, left, right0, y0)));
   __syncthreads();

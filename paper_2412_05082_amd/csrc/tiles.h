@@ -164,5 +164,47 @@ __device__ __forceinline__ T band_row(const T* __restrict__ tab, const T* __rest
   }
 }
 
+// LDS copies of a level's fast-diagonalisation data, every global load of
+// a thread issued before its first LDS store: sQ = the four
+// eigenbases (4 n^2), sLam = their eigenvalues (4 n), and the interior
+// patch's inverse eigenvalue sums sD[ap][c] = 1 / (lambda_c + lambda_ap).
+template <typename T, int n, int NTH>
+__device__ __forceinline__ void stage_eig(const T* __restrict__ Qg, const T* __restrict__ lamg, T* __restrict__ sQ,
+                                          T* __restrict__ sLam, T* __restrict__ sD) {
+  constexpr int NN = n * n, LQ = (4 * NN + NTH - 1) / NTH, LL = (4 * n + NTH - 1) / NTH, LD = (NN + NTH - 1) / NTH;
+  T q[LQ], l[LL], da[LD], db[LD];
+#pragma unroll
+  for (int u = 0; u < LQ; ++u) {
+    const int e = threadIdx.x + u * NTH;
+    q[u] = e < 4 * NN ? Qg[e] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < LL; ++u) {
+    const int e = threadIdx.x + u * NTH;
+    l[u] = e < 4 * n ? lamg[e] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < LD; ++u) {
+    const int e = threadIdx.x + u * NTH;
+    da[u] = e < NN ? lamg[e % n] : T(1);
+    db[u] = e < NN ? lamg[e / n] : T(1);
+  }
+#pragma unroll
+  for (int u = 0; u < LQ; ++u) {
+    const int e = threadIdx.x + u * NTH;
+    if (e < 4 * NN) sQ[e] = q[u];
+  }
+#pragma unroll
+  for (int u = 0; u < LL; ++u) {
+    const int e = threadIdx.x + u * NTH;
+    if (e < 4 * n) sLam[e] = l[u];
+  }
+#pragma unroll
+  for (int u = 0; u < LD; ++u) {
+    const int e = threadIdx.x + u * NTH;
+    if (e < NN) sD[e] = T(1) / (da[u] + db[u]);  // [ap][c]
+  }
+}
+
 }  // namespace tile
 }  // namespace c0ip
