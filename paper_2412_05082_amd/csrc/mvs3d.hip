@@ -79,6 +79,7 @@ __device__ __forceinline__ void vertex3(const Colour3& k, int q, int& vx, int& v
 template <int K> struct ColourPatches3 {
   static constexpr int n = 2 * K - 1;
   static constexpr int NPW = kThreads / (n * n) > 0 ? kThreads / (n * n) : 1;
+  static_assert(4 * n <= kThreads, "one eigenvalue per thread");
 };
 
 template <typename T, int K>
@@ -94,16 +95,44 @@ __global__ __launch_bounds__(kThreads) void mvs3d_colour_kernel(const T* __restr
   const int np = min(NPW, col.total - q0);
   if (np <= 0) return;
   const size_t s1 = n1, s2 = (size_t)n1 * n1;
-  // gather r on the patches' nodes, x fastest
-  for (int e = threadIdx.x; e < np * N3; e += kThreads) {
-    const int p = e / N3, loc = e - p * N3;
-    const int zz = loc / NN, yy = (loc / n) % n, xx = loc % n;
-    int vx, vy, vz;
-    vertex3(col, q0 + p, vx, vy, vz);
-    sB[e] = r[(size_t)((vz - 1) * K + 1 + zz) * s2 + (size_t)((vy - 1) * K + 1 + yy) * s1 + (vx - 1) * K + 1 + xx];
+  // gather r on the patches' nodes (x fastest), and x there for the final
+  // update (no other workgroup of the colour reads or writes those nodes):
+  // every global load is issued before the first LDS store
+  constexpr int NL = (NPW * N3 + kThreads - 1) / kThreads, LQ = (4 * NN + kThreads - 1) / kThreads;
+  T rv[NL], xv[NL], qv[LQ];
+  size_t gi[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int e = threadIdx.x + u * kThreads;
+    rv[u] = xv[u] = T(0);
+    gi[u] = 0;
+    if (e < np * N3) {
+      const int p = e / N3, loc = e - p * N3;
+      const int zz = loc / NN, yy = (loc / n) % n, xx = loc % n;
+      int vx, vy, vz;
+      vertex3(col, q0 + p, vx, vy, vz);
+      gi[u] = (size_t)((vz - 1) * K + 1 + zz) * s2 + (size_t)((vy - 1) * K + 1 + yy) * s1 + (vx - 1) * K + 1 + xx;
+      rv[u] = r[gi[u]];
+      xv[u] = x[gi[u]];
+    }
   }
-  for (int e = threadIdx.x; e < 4 * NN; e += kThreads) sQ[e] = Qg[e];
-  for (int e = threadIdx.x; e < 4 * n; e += kThreads) sLam[e] = lamg[e];
+#pragma unroll
+  for (int u = 0; u < LQ; ++u) {
+    const int e = threadIdx.x + u * kThreads;
+    qv[u] = e < 4 * NN ? Qg[e] : T(0);
+  }
+  const T lv = threadIdx.x < 4 * n ? lamg[threadIdx.x] : T(0);
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int e = threadIdx.x + u * kThreads;
+    if (e < np * N3) sB[e] = rv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < LQ; ++u) {
+    const int e = threadIdx.x + u * kThreads;
+    if (e < 4 * NN) sQ[e] = qv[u];
+  }
+  if (threadIdx.x < 4 * n) sLam[threadIdx.x] = lv;
   __syncthreads();
   // forward along x: sA[z][y][c] = sum_c' Qx[c'][c] sB[z][y][c']
   for (int it = threadIdx.x; it < np * NN; it += kThreads) {
@@ -209,14 +238,10 @@ __global__ __launch_bounds__(kThreads) void mvs3d_colour_kernel(const T* __restr
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < np * N3; e += kThreads) {
-    const int p = e / N3, loc = e - p * N3;
-    const int zz = loc / NN, yy = (loc / n) % n, xx = loc % n;
-    int vx, vy, vz;
-    vertex3(col, q0 + p, vx, vy, vz);
-    const size_t g =
-        (size_t)((vz - 1) * K + 1 + zz) * s2 + (size_t)((vy - 1) * K + 1 + yy) * s1 + (vx - 1) * K + 1 + xx;
-    x[g] = x[g] + omega * sA[e];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int e = threadIdx.x + u * kThreads;
+    if (e < np * N3) x[gi[u]] = xv[u] + omega * sA[e];
   }
 }
 
