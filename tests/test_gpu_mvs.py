@@ -163,6 +163,22 @@ def test_mvs_residual_modes_match_oracle(k, N, local_solver, tdt):
             check(f"mode {m} V-cycle", rel_l2(z, refz), bars[2])
 
 
+@pytest.mark.parametrize("k,N", [(3, 32), (7, 8)])
+@pytest.mark.parametrize("tdt", [torch.float64, torch.float32])
+def test_mvs_in_launch_residual_is_deterministic(k, N, tdt):
+    """The colour kernel updates x in place while other workgroups of the
+    launch read x: two runs of S(x, b), S(0, b) and the V-cycle with the
+    residual formed in the launch agree bit for bit (a workgroup reading a
+    node another one writes would show up here as run-to-run differences)."""
+    say("mvs in-launch determinism", k, N, tdt)
+    x, b = vectors(2, k, N)
+    xd, bd = dev(x, tdt), dev(b, tdt)
+    first = _mvs_outputs(2, k, N, 1, xd, bd, tdt)
+    second = _mvs_outputs(2, k, N, 1, xd, bd, tdt)
+    for name, u, v in zip(("S(x,b)", "S(0,b)", "V-cycle"), first, second):
+        assert np.array_equal(u, v), name
+
+
 @pytest.mark.timeout(300)
 def test_mvs_residual_modes_above_the_switch():
     """2D Q2 512^2 (1,050,625 DoFs, above the 2^20 switch): the automatic
