@@ -135,3 +135,20 @@ def test_meshes_beyond_the_dof_limit_are_rejected_before_any_device_call():
     meshes = (P.MeshDesc * 1)(P.MeshDesc(2, 16384, 3, 0.0))
     rhs = (C.c_int * 1)(1)
     assert lib.c0ip_batch_create(meshes, rhs, 1, None, None, C.byref(h)) == -1
+
+
+def test_bad_multigrid_options_are_rejected_before_any_device_call():
+    """c0ip_create checks every option before it touches the GPU: an
+    mvs_residual outside 0..2 (and the other out-of-range fields) give
+    C0IP_EINVAL with a message naming the field."""
+    import ctypes as C
+    lib = P.load_library()
+    h = C.c_void_p()
+    mesh = P.MeshDesc(2, 8, 3, 0.0)
+    base = dict(omega=1.0, pre_steps=1, post_steps=1, vcycle_dtype=P.C0IP_F32, coarse_mode=0, scatter_mode=0,
+                tail_levels=-1, smoother=1, local_solver=0, mvs_residual=0)
+    for field, value, word in [("mvs_residual", 3, b"mvs_residual"), ("mvs_residual", -1, b"mvs_residual"),
+                               ("smoother", 2, b"smoother"), ("coarse_mode", 2, b"coarse_mode")]:
+        opts = P.MgOpts(**dict(base, **{field: value}))
+        assert lib.c0ip_create(C.byref(mesh), C.byref(opts), None, C.byref(h)) == -1, (field, value)
+        assert word in lib.c0ip_last_error(), lib.c0ip_last_error()
