@@ -105,8 +105,8 @@ typedef struct {
  *   residual b - A x.  1 = in the colour's own launch, on its patches'
  *   rows only (x staged in LDS around each patch); 2 = a full residual pass
  *   with the tiled operator before each colour's solves; 0 = automatic (1 on
- *   levels under 2^20 DoFs, where launches dominate, 2 on finer ones).  The
- *   modes form the same sums and agree to rounding.  Ignored
+ *   levels under 1.5 * 2^20 DoFs, where launches dominate, 2 on finer
+ *   ones).  The modes form the same sums and agree to rounding.  Ignored
  *   in 3D (always 2) and by the additive smoother; batched solves take 0
  *   only.  Other values: C0IP_EINVAL. */
 typedef struct {

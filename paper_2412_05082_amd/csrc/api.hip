@@ -305,7 +305,7 @@ void c0ip_problem::patch_step(int l, const T* r, const T* x_in, T* x_out, T om) 
 // `steps` steps of the coloured multiplicative smoother on level l, in
 // place on x: per colour c = 0..2^(d+1)-1, r = b - A x (r = b for the first colour
 // of a step from x = 0), then x += omega * (local solves of colour c).  On
-// 2D levels under 2^20 DoFs one launch per colour forms r on the colour's
+// 2D levels under 1.5 * 2^20 DoFs one launch per colour forms r on the colour's
 // patch rows only; elsewhere r is a full residual pass (work vector r)
 // before each colour.
 template <typename T>
@@ -314,16 +314,19 @@ void c0ip_problem::smooth_mvs(int l, const T* b, T* x, T* r, int steps, bool x_i
   const int Nl = lv[l]->N;
   const T om = (T)mg.omega;
   const int ncol = 1 << (dim + 1);
-  // mvs_residual 0 (automatic): on 2D levels under 2^20 DoFs one launch per colour forms the residual on
-  // the colour's patch rows (it halves the launches, which bound these levels); on finer levels a full
-  // residual pass with the tiled operator precedes the colour's solves (there the operator's efficiency
-  // wins: Q3 512^2 315 against 357 us per float64 step; 256^2 183 against 146 us)
+  // mvs_residual 0 (automatic): on 2D levels under 1.5 * 2^20 DoFs one launch per colour forms the residual
+  // on the colour's patch rows (it halves the launches, which bound these levels); on finer levels a full
+  // residual pass with the tiled operator precedes the colour's solves, where the operator's efficiency
+  // wins. Measured per float64 step, in-launch against residual pass, in us: Q2 512^2 (1.05 M DoFs) 184
+  // against 226, Q4 256^2 (1.05 M) 246 against 262, Q5 256^2 (1.64 M) 398 against 383, Q3 512^2 (2.36 M)
+  // 357 against 315, Q7 256^2 (3.21 M) 1282 against 925.
+  constexpr int64_t kMvsInLaunchBelow = int64_t(3) << 19;
   for (int s = 0; s < steps; ++s)
     for (int c = 0; c < ncol; ++c) {
       const bool zero = s == 0 && c == 0 && x_is_zero;
       if (zero) check(c0ip::launch_fill_t<T>(lv[l]->ntot, T(0), x, stream), "fill");
       const bool fused =
-          dim == 2 && (mg.mvs_residual == 1 || (mg.mvs_residual == 0 && lv[l]->ntot < (int64_t(1) << 20)));
+          dim == 2 && (mg.mvs_residual == 1 || (mg.mvs_residual == 0 && lv[l]->ntot < kMvsInLaunchBelow));
       const T* rc = zero ? b : (fused ? nullptr : r);
       if (!zero && !fused) check(c0ip::launch_apply<T, T>(dim, k, Nl, w.coef, x, b, r, stream), "residual");
       if (dim == 2 && mg.local_solver == 1)

@@ -181,13 +181,13 @@ def test_mvs_in_launch_residual_is_deterministic(k, N, tdt):
 
 @pytest.mark.timeout(300)
 def test_mvs_residual_modes_above_the_switch():
-    """2D Q2 512^2 (1,050,625 DoFs, above the 2^20 switch): the automatic
+    """2D Q2 1024^2 (4,198,401 DoFs, above the 1.5 * 2^20 switch): the automatic
     mode uses the full residual pass on the finest level and the in-launch
     residual below; the two fixed modes agree with it to the oracle bars of
     the tests above (taken on 64^2, the oracle's floors depend on k, hardly
     on N), in both precisions."""
-    dim, k, N = 2, 2, 512
-    assert (k * N + 1) ** 2 >= 2 ** 20 > (k * N // 2 + 1) ** 2
+    dim, k, N = 2, 2, 1024
+    assert (k * N + 1) ** 2 >= 3 * 2 ** 19 > (k * N // 2 + 1) ** 2
     say("mvs residual modes above the switch", dim, k, N)
     g = torch.Generator(device="cuda")
     g.manual_seed(77)
